@@ -1,0 +1,228 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the bulk incremental connectivity hot path.
+
+One step = one pass of the whole path over the R-MAT scale-24 stream
+(n = 2^24 vertices, 2^28 edges with a=.57 b=.19 c=.19 d=.05 and randomly
+permuted ids, streamed as minibatches of log-uniform size in [2^16, 2^24],
+each followed by a Bulk-Query of 2^20 uniform random pairs): reset the forest,
+then every Bulk-Update and Bulk-Query in stream order, then the min-id label
+pass and the component count.  Inputs are generated on the host and resident
+in HBM before timing starts.
+
+Prints ONE JSON line.  `value` is (update edges + query pairs) per second of
+wall clock over the timed steps; the per-operation rates come from HIP events
+on the graph's stream.  Also reported: the update kernel against the HBM
+roofline (algorithmic bytes), against a measured random-gather roofline, and
+the CPU oracle's rate on a bounded sample of the same stream.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Bulk-Update edges/s + Bulk-Query queries/s, batched vs plain; p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per update edge: 8 B of ids streamed + two random 4-B parent reads
+UPDATE_BYTES_PER_EDGE = 16
+PAPER_CONTEXT = {"value": 167.68e6, "unit": "edges/s",
+                 "what": "Bulk-Update, rMat16 (2^27 vertices, 1.6e9 edges), b=10M, 20-core Xeon (Table 3)"}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1602_05232_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel_tag: str):
+    """HBM traffic per launch from the committed counter summary, if it was
+    taken on the current kernel sources."""
+    p = os.path.join(ROOT, "profiles", "pmc_%s.txt" % kernel_tag)
+    if not os.path.exists(p):
+        return None
+    kv = {}
+    for line in open(p):
+        if ":" in line and not line.startswith(" "):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_digest") != source_digest():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def pct(xs, p):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = min(len(xs) - 1, max(0, int(round(p / 100.0 * (len(xs) - 1)))))
+    return xs[k]
+
+
+def cpu_baseline(s, budget_s: float):
+    """The oracle, as it is, on a prefix of the same stream (one thread)."""
+    import oracle
+    uf = oracle.UnionFind(s.n)
+    edges = queries = 0
+    t0 = time.perf_counter()
+    nb = 0
+    for i in range(s.num_batches):
+        uf.bulk_update(s.batch(i))
+        uf.bulk_query(s.query(i))
+        edges += int(s.eoff[i + 1] - s.eoff[i])
+        queries += int(s.qoff[i + 1] - s.qoff[i])
+        nb = i + 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": (edges + queries) / dt, "unit": "edges+queries/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d of %d minibatches with their query batches (%d edges, %d queries, %.1f s)"
+                      % (nb, s.num_batches, edges, queries, dt),
+            "update_edges": edges, "queries": queries, "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--scale", type=int, default=24, help="R-MAT scale (24 = the headline workload)")
+    ap.add_argument("--options", default="", help="JSON dict of cc_set_option overrides")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-roofline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on one GPU only; --gpus %d (WORLD_SIZE=%d) is not supported"
+              % (args.gpus, world), file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1602_05232_amd import build as hipbuild
+    if not os.path.exists(hipbuild.OUT):
+        import __graft_entry__
+        __graft_entry__.build()
+    import paper_1602_05232_amd as ccgpu
+    from paper_1602_05232_amd import roofline, tuning
+
+    t = time.perf_counter()
+    s = synth.rmat_stream(scale=args.scale)
+    log("generated %s: n=%d edges=%d minibatches=%d queries=%d in %.1fs"
+        % (s.name, s.n, len(s.edges), s.num_batches, len(s.queries), time.perf_counter() - t))
+    M, Qn, nb = len(s.edges), len(s.queries), s.num_batches
+
+    opts = tuning.plain_options(s.n, workload="rmat")
+    if args.options:
+        opts.update(json.loads(args.options))
+    E = torch.from_numpy(s.edges).cuda()
+    Q = torch.from_numpy(s.queries).cuda()
+    out = torch.empty(Qn, dtype=torch.uint8, device="cuda")
+    lab = torch.empty(s.n, dtype=torch.int32, device="cuda")
+    eoff = [int(x) for x in s.eoff]
+    qoff = [int(x) for x in s.qoff]
+    g = ccgpu.Graph(s.n, **opts)
+    g.reserve(max(eoff[i + 1] - eoff[i] for i in range(nb)))
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(nb)]
+
+    def step(k):
+        g.reset()
+        for i in range(nb):
+            ev[i][0].record(stream)
+            g.bulk_update(E[eoff[i]:eoff[i + 1]])
+            ev[i][1].record(stream)
+            g.bulk_query(Q[qoff[i]:qoff[i + 1]], out=out[qoff[i]:qoff[i + 1]])
+            ev[i][2].record(stream)
+        g.labels(out=lab)
+        return g.num_components()  # waits for the stream
+
+    for k in range(args.warmup):
+        c = step(k)
+        log("warmup step %d done: components=%d" % (k, c))
+    torch.cuda.synchronize()
+    upd_t, qry_t, upd_lat = [], [], []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        c = step(k)
+        tu = [ev[i][0].elapsed_time(ev[i][1]) / 1e3 for i in range(nb)]
+        tq = [ev[i][1].elapsed_time(ev[i][2]) / 1e3 for i in range(nb)]
+        upd_t.append(sum(tu))
+        qry_t.append(sum(tq))
+        upd_lat.extend(x * 1e3 for x in tu)
+        log("step %d done: components=%d update %.4fs query %.4fs" % (k, c, upd_t[-1], qry_t[-1]))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    rc = g.sync()
+    if rc != 0:
+        raise SystemExit("device reported status %d" % rc)
+    steps = max(1, args.steps)
+    upd_rate = steps * M / sum(upd_t)
+    qry_rate = steps * Qn / sum(qry_t)
+
+    res = {
+        "metric": METRIC, "value": steps * (M + Qn) / wall, "unit": "edges+queries/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "rmat%d-plain" % args.scale, "n": s.n, "edges": M, "minibatches": nb,
+                   "minibatch_sizes": "log-uniform in [2^16, 2^24]", "queries_per_minibatch": qoff[1] - qoff[0],
+                   "rmat_abcd": [0.57, 0.19, 0.19, 0.05], "form": "plain", "options": opts},
+        "update_edges_per_s": upd_rate, "queries_per_s": qry_rate,
+        "update_op_ms": {"p50": pct(upd_lat, 50), "p99": pct(upd_lat, 99)},
+        "components": c, "paper_context": PAPER_CONTEXT,
+    }
+    if not args.no_roofline:
+        tag = "update_fused_rmat%d" % args.scale if opts.get("update_mode", 0) == 0 else \
+            "update_split_rmat%d" % args.scale
+        achieved = UPDATE_BYTES_PER_EDGE * upd_rate / 1e9
+        res["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic(tag),
+                           "kernel": "k_update_fused" if opts.get("update_mode", 0) == 0 else
+                           "k_filter+k_link_live+k_compress_live",
+                           "bytes_per_edge": UPDATE_BYTES_PER_EDGE,
+                           "avg_launch_ms": sum(upd_t) / (steps * nb) * 1e3,
+                           "bytes_per_launch": UPDATE_BYTES_PER_EDGE * M / nb}
+        del E, Q
+        torch.cuda.empty_cache()
+        G = roofline.gather_rate(s.n)
+        Gbig = roofline.gather_rate(1 << 30, count=1 << 27)
+        Bs = roofline.stream_bandwidth()
+        Eroof = roofline.edge_roofline(G, Bs)
+        res["gather_roofline"] = {
+            "G_gathers_per_s_table_n": G, "G_gathers_per_s_table_2^30": Gbig, "stream_read_GBs": Bs / 1e9,
+            "E_roof_edges_per_s": Eroof, "frac": upd_rate / Eroof,
+            "E_roof_beyond_cache_edges_per_s": roofline.edge_roofline(Gbig, Bs),
+            "note": "E_roof = 1/(2/G + 8/B_s): two random parent reads and 8 streamed bytes per edge"}
+        log("gather roofline: G(n)=%.3g/s G(2^30)=%.3g/s B_s=%.1f GB/s E_roof=%.3g e/s frac=%.3f"
+            % (G, Gbig, Bs / 1e9, Eroof, upd_rate / Eroof))
+    g.close()
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(s, args.cpu_budget)
+        log("cpu baseline: %s" % res["cpu_baseline"]["sample"])
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

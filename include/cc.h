@@ -1,0 +1,166 @@
+/*
+ * cc.h -- bulk-parallel incremental graph connectivity on one AMD MI355X.
+ *
+ * The problem is the one of Simsiri, Tangwongsan, Tirthapura and Wu,
+ * "Work-Efficient Parallel and Incremental Graph Connectivity", Section 1
+ * (Model): a fixed vertex set V = {0, ..., n-1} receives a stream of edge
+ * minibatches A_1, A_2, ...; after A_t the graph is G_t = (V, A_1 u ... u A_t).
+ * Two bulk operations act on it:
+ *   - Bulk-Update(A_i) adds a minibatch of edges;
+ *   - Bulk-Query(pairs) answers, for each vertex pair, whether the pair is
+ *     connected in the edges seen so far.
+ * A bulk operation completes before the next begins (Section 1).  Here that
+ * order is the order of calls on the graph's HIP stream: every call is
+ * asynchronous and stream ordered, and no call waits for the device unless
+ * its comment says so.
+ *
+ * State is one int32 union-find parent array of n entries in device memory
+ * (O(n) words, Theorem 1 of Section 4), owned by the graph handle.
+ *
+ * Conventions for every call:
+ *   - Vertex ids are int32 in [0, n).  Edge and pair arrays are int32[k][2]
+ *     (u0, v0, u1, v1, ...), 8-byte aligned, in DEVICE memory owned by the
+ *     caller; they must stay valid until the stream has run the call.
+ *   - An edge or pair holding an id outside [0, n) is skipped: the edge is
+ *     not applied, the pair's answer is 0.  All other items are processed as
+ *     usual.  The skip is latched on the device and reported once by the next
+ *     cc_sync() as CC_ERANGE.
+ *   - Argument errors (NULL handle or pointer with a nonzero count, negative
+ *     count) return CC_EINVAL at once and enqueue nothing.
+ *   - A count of 0 is a no-op.
+ *   - A handle is not thread safe; different handles are independent.
+ *   - Return codes are CC_OK or one of the negative CC_E* codes; the text of
+ *     the last failure in the calling thread is available from
+ *     cc_last_error().
+ */
+#ifndef CC_H
+#define CC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cc_graph cc_graph;
+
+enum cc_status {
+  CC_OK = 0,
+  CC_EINVAL = -1,   /* bad argument; nothing was enqueued */
+  CC_ENOMEM = -2,   /* device or host allocation failed */
+  CC_ERANGE = -3,   /* an id outside [0, n) was skipped (reported by cc_sync) */
+  CC_EDEVICE = -4,  /* a HIP runtime call failed */
+  CC_ECORRUPT = -5  /* a find exceeded n steps (the parent array holds a cycle),
+                       or a state image given to cc_load is not a valid forest */
+};
+
+/* Tuning options (cc_set_option).  None changes any result. */
+enum cc_option {
+  /* Bulk-Update schedule.  0 = fused: one kernel finds both roots and links
+   * them with a compare-and-swap in place.  1 = split: a filter kernel
+   * relabels edges by their roots and compacts the pairs with distinct roots
+   * (Algorithm 2, lines 1-2) into a live list, a link kernel joins the live
+   * root pairs, a compress kernel points the linked roots at their new root.
+   * Default 0. */
+  CC_OPT_UPDATE_MODE = 1,
+  CC_OPT_BLOCK = 2,          /* threads per block, multiple of 64 in [64, 1024]; default 256 */
+  CC_OPT_ITEMS = 3,          /* edges (or pairs) per thread: 1, 2, 4 or 8, or 0 = chosen per
+                                call from the item count (default 0) */
+  CC_OPT_QUERY_HALVING = 4,  /* 1: query finds also halve paths (default); 0: read-only */
+  CC_OPT_COMPRESS_EVERY = 5, /* k > 0: after every k-th update point every vertex at its
+                                root (full pass over n); 0 = never (default) */
+  CC_OPT_HOOK = 6,           /* linking order: 0 = by vertex id, the smaller id becomes
+                                the root (default); 1 = by a hashed priority (fmix32) */
+  CC_OPT_GRID_CAP = 7,       /* upper bound on blocks per launch (grid-stride beyond it);
+                                default 4096 */
+  /* Fused schedule: 1 = record the roots each update links and afterwards
+   * point every vertex on their paths straight at the root (the "pragmatic"
+   * path compression of Section 6.1, limited to what the minibatch changed);
+   * 0 = rely on path halving alone.  Default 1. */
+  CC_OPT_COMPRESS_LINKED = 8
+};
+
+/* Create a graph on vertices [0, n), 1 <= n <= 2^31 - 1, every vertex its own
+ * component (parent[v] = v).  Uses the current HIP device and the null
+ * stream until cc_set_stream.  Waits for the initialisation to finish.
+ * Returns NULL on failure (see cc_last_error()).  Ownership: the caller
+ * releases the handle with cc_destroy. */
+cc_graph* cc_create(int64_t n);
+
+/* Release the handle and its device memory.  Waits for the graph's stream. */
+int cc_destroy(cc_graph* g);
+
+/* Issue all later work of g on `stream` (a hipStream_t; NULL = null stream).
+ * The caller keeps ownership of the stream and must not destroy it while g
+ * uses it. */
+int cc_set_stream(cc_graph* g, void* stream);
+
+/* Set a tuning option (enum cc_option).  CC_EINVAL for an unknown key or a
+ * value out of range. */
+int cc_set_option(cc_graph* g, int key, int64_t value);
+int cc_get_option(cc_graph* g, int key, int64_t* value);
+
+/* Pre-size the scratch used by the split update schedule for minibatches of
+ * up to max_batch edges, so that no later call allocates.  Waits for the
+ * stream if an existing buffer is replaced. */
+int cc_reserve(cc_graph* g, int64_t max_batch);
+
+/* Restore the initial state (every vertex alone) without reallocating. */
+int cc_reset(cc_graph* g);
+
+/* Bulk-Update (Section 1; Algorithm 2 of Section 4.2 computes the same
+ * connectivity): add the m edges of `edges` (device int32[m][2]).  Edges are
+ * undirected; self-loops and repeated edges are allowed and change nothing.
+ * The order of edges within the minibatch does not matter (Section 4.2,
+ * correctness of Simple-Bulk-Update).  May allocate split-schedule scratch if
+ * m exceeds the reserved size (see cc_reserve). */
+int cc_bulk_update(cc_graph* g, const int32_t* edges, int64_t m);
+
+/* Bulk-Query (Algorithm 1, Simple-Bulk-Query): out[i] = 1 if pairs[i] are
+ * connected by the edges of all earlier updates on g, else 0.  pairs is
+ * device int32[q][2], out is device uint8[q], written in input order.  A pair
+ * (u, u) answers 1. */
+int cc_bulk_query(cc_graph* g, const int32_t* pairs, int64_t q, uint8_t* out);
+
+/* Canonical component labels: out[v] = the smallest vertex id connected to v
+ * (the paper's find returns "an identifier" of the component, Section 4;
+ * this fixes it to the minimum).  out is device int32[n].  Also points
+ * every vertex directly at its root. */
+int cc_labels(cc_graph* g, int32_t* out);
+
+/* Number of connected components of G_t, counting isolated vertices
+ * (n minus the number of successful links).  Waits for the stream;
+ * *out is a host int64. */
+int cc_num_components(cc_graph* g, int64_t* out);
+
+/* Number of roots (vertices v with parent[v] == v), counted by a pass over
+ * the parent array.  Equals cc_num_components; kept as an independent check.
+ * Waits for the stream. */
+int cc_count_roots(cc_graph* g, int64_t* out);
+
+/* Wait for all work issued on g's stream; then report, once, a skipped id
+ * (CC_ERANGE) or a corrupt forest (CC_ECORRUPT) latched since the last
+ * cc_sync, and clear it.  CC_EDEVICE if the stream failed. */
+int cc_sync(cc_graph* g);
+
+/* State image for checkpoint and restore: cc_state_bytes(g) bytes laid out as
+ * int64 n, int64 successful links, int32 parent[n].  cc_save writes it to a
+ * caller-owned HOST buffer and waits for the stream; cc_load reads it back
+ * (same n), checks that it is a forest under g's linking order (else
+ * CC_ECORRUPT and g is unchanged), and waits for the copy. */
+int64_t cc_state_bytes(const cc_graph* g);
+int cc_save(cc_graph* g, void* host_buf);
+int cc_load(cc_graph* g, const void* host_buf);
+
+/* Vertex count of g (0 for NULL). */
+int64_t cc_num_vertices(const cc_graph* g);
+
+/* Text of a status code, and of the last failure in the calling thread. */
+const char* cc_strerror(int code);
+const char* cc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CC_H */

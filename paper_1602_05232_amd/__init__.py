@@ -1,0 +1,6 @@
+"""Bulk-parallel incremental graph connectivity on AMD MI355X (gfx950).
+
+Hot path: Bulk-Update and Bulk-Query over a union-find parent array in HBM,
+as hand-written HIP kernels behind the C ABI of include/cc.h (libcc.so).
+"""
+from .cc import CCError, Graph, lib  # noqa: F401

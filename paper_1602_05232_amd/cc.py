@@ -1,0 +1,210 @@
+"""Python binding of libcc.so (include/cc.h): argument marshalling only.
+
+Every step of Bulk-Update, Bulk-Query and the label pass runs in the HIP
+kernels of libcc.so; this module only turns torch device tensors into raw
+pointers and HIP streams into handles.  There is no fallback: if the library
+is not built, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # loads torch's HIP runtime first, so libcc.so binds to the same one
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcc.so")
+
+CC_OK, CC_EINVAL, CC_ENOMEM, CC_ERANGE, CC_EDEVICE, CC_ECORRUPT = 0, -1, -2, -3, -4, -5
+OPT_UPDATE_MODE, OPT_BLOCK, OPT_ITEMS, OPT_QUERY_HALVING = 1, 2, 3, 4
+OPT_COMPRESS_EVERY, OPT_HOOK, OPT_GRID_CAP, OPT_COMPRESS_LINKED = 5, 6, 7, 8
+_OPT_NAMES = {"update_mode": OPT_UPDATE_MODE, "block": OPT_BLOCK, "items": OPT_ITEMS,
+              "query_halving": OPT_QUERY_HALVING, "compress_every": OPT_COMPRESS_EVERY,
+              "hook": OPT_HOOK, "grid_cap": OPT_GRID_CAP, "compress_linked": OPT_COMPRESS_LINKED}
+
+# Every symbol include/cc.h declares, with (restype, argtypes).
+_vp, _i64, _i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+SIGNATURES = {
+    "cc_create": (_vp, [_i64]),
+    "cc_destroy": (_i32, [_vp]),
+    "cc_set_stream": (_i32, [_vp, _vp]),
+    "cc_set_option": (_i32, [_vp, _i32, _i64]),
+    "cc_get_option": (_i32, [_vp, _i32, ctypes.POINTER(_i64)]),
+    "cc_reserve": (_i32, [_vp, _i64]),
+    "cc_reset": (_i32, [_vp]),
+    "cc_bulk_update": (_i32, [_vp, _vp, _i64]),
+    "cc_bulk_query": (_i32, [_vp, _vp, _i64, _vp]),
+    "cc_labels": (_i32, [_vp, _vp]),
+    "cc_num_components": (_i32, [_vp, ctypes.POINTER(_i64)]),
+    "cc_count_roots": (_i32, [_vp, ctypes.POINTER(_i64)]),
+    "cc_sync": (_i32, [_vp]),
+    "cc_state_bytes": (_i64, [_vp]),
+    "cc_save": (_i32, [_vp, _vp]),
+    "cc_load": (_i32, [_vp, _vp]),
+    "cc_num_vertices": (_i64, [_vp]),
+    "cc_strerror": (ctypes.c_char_p, [_i32]),
+    "cc_last_error": (ctypes.c_char_p, []),
+}
+
+# include/cc_bench.h (memory-system microbenchmarks for roofline denominators)
+BENCH_SIGNATURES = {
+    "ccb_gather": (_i32, [_vp, _i64, _i64, ctypes.c_uint32, _vp, _vp]),
+    "ccb_stream_read": (_i32, [_vp, _i64, _vp, _vp]),
+    "ccb_copy": (_i32, [_vp, _vp, _i64, _vp]),
+    "ccb_cas": (_i32, [_vp, _i64, _i64, ctypes.c_uint32, _vp]),
+}
+
+
+class CCError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s (%d): %s" % (_name(code), code, msg))
+        self.code = code
+
+
+def _name(code):
+    return {0: "CC_OK", -1: "CC_EINVAL", -2: "CC_ENOMEM", -3: "CC_ERANGE", -4: "CC_EDEVICE",
+            -5: "CC_ECORRUPT"}.get(code, "CC_?")
+
+
+def load_library(path: str = LIB_PATH, declare=None):
+    declare = declare if declare is not None else {**SIGNATURES, **BENCH_SIGNATURES}
+    if not os.path.exists(path):
+        raise ImportError("%s is not built; run __graft_entry__.build() first" % path)
+    L = ctypes.CDLL(path)
+    for name, (res, args) in declare.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    return L
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = load_library()
+    return _lib
+
+
+def _check(rc: int):
+    if rc != CC_OK:
+        raise CCError(rc, lib().cc_last_error().decode(errors="replace"))
+    return rc
+
+
+def _pairs_ptr(t: torch.Tensor, what: str) -> int:
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.int32):
+        raise TypeError("%s must be a CUDA int32 tensor" % what)
+    if t.numel() and not (t.dim() == 2 and t.shape[1] == 2 and t.is_contiguous()):
+        raise ValueError("%s must be a contiguous [k, 2] tensor" % what)
+    return t.data_ptr()
+
+
+def stream_handle(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+class Graph:
+    """A union-find forest over vertices [0, n) in device memory.
+
+    Calls are asynchronous and ordered on `stream` (default: the current
+    torch stream at construction)."""
+
+    def __init__(self, n: int, stream=None, **options):
+        self._h = None
+        L = lib()
+        h = L.cc_create(int(n))
+        if not h:
+            raise CCError(CC_EINVAL, L.cc_last_error().decode(errors="replace"))
+        self._h = h
+        self.n = int(n)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        _check(L.cc_set_stream(h, stream_handle(self.stream)))
+        for k, v in options.items():
+            self.set_option(k, v)
+
+    def close(self):
+        if self._h:
+            lib().cc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self) -> int:
+        return self._h
+
+    def set_option(self, key, value: int):
+        k = _OPT_NAMES[key] if isinstance(key, str) else int(key)
+        _check(lib().cc_set_option(self._h, k, int(value)))
+
+    def get_option(self, key) -> int:
+        k = _OPT_NAMES[key] if isinstance(key, str) else int(key)
+        v = ctypes.c_int64()
+        _check(lib().cc_get_option(self._h, k, ctypes.byref(v)))
+        return v.value
+
+    def reserve(self, max_batch: int):
+        _check(lib().cc_reserve(self._h, int(max_batch)))
+
+    def reset(self):
+        _check(lib().cc_reset(self._h))
+
+    def bulk_update(self, edges: torch.Tensor):
+        p = _pairs_ptr(edges, "edges")
+        _check(lib().cc_bulk_update(self._h, p, edges.shape[0] if edges.numel() else 0))
+
+    def bulk_query(self, pairs: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        p = _pairs_ptr(pairs, "pairs")
+        q = pairs.shape[0] if pairs.numel() else 0
+        if out is None:
+            out = torch.empty(q, dtype=torch.uint8, device=pairs.device)
+        assert out.dtype == torch.uint8 and out.is_cuda and out.numel() >= q and out.is_contiguous()
+        _check(lib().cc_bulk_query(self._h, p, q, out.data_ptr()))
+        return out
+
+    def labels(self, out: torch.Tensor | None = None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        assert out.dtype == torch.int32 and out.is_cuda and out.numel() >= self.n and out.is_contiguous()
+        _check(lib().cc_labels(self._h, out.data_ptr()))
+        return out
+
+    def num_components(self) -> int:
+        v = ctypes.c_int64()
+        _check(lib().cc_num_components(self._h, ctypes.byref(v)))
+        return v.value
+
+    def count_roots(self) -> int:
+        v = ctypes.c_int64()
+        _check(lib().cc_count_roots(self._h, ctypes.byref(v)))
+        return v.value
+
+    def sync(self) -> int:
+        """Wait for the stream; returns CC_OK, CC_ERANGE or CC_ECORRUPT
+        (latched since the last sync) and raises on a device error."""
+        rc = lib().cc_sync(self._h)
+        if rc in (CC_OK, CC_ERANGE, CC_ECORRUPT):
+            return rc
+        return _check(rc)
+
+    def save(self) -> bytearray:
+        buf = bytearray(int(lib().cc_state_bytes(self._h)))
+        cbuf = (ctypes.c_char * len(buf)).from_buffer(buf)
+        _check(lib().cc_save(self._h, ctypes.addressof(cbuf)))
+        return buf
+
+    def load(self, buf) -> None:
+        buf = bytearray(buf)
+        cbuf = (ctypes.c_char * len(buf)).from_buffer(buf)
+        if len(buf) != lib().cc_state_bytes(self._h):
+            raise CCError(CC_EINVAL, "state image has the wrong size")
+        _check(lib().cc_load(self._h, ctypes.addressof(cbuf)))

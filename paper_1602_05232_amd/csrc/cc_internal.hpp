@@ -1,0 +1,114 @@
+// Host-side helpers shared by the library's translation units.
+#pragma once
+
+#include <stdarg.h>
+#include <stdint.h>
+
+#include "../../include/cc.h"
+
+void cc_set_error(const char* fmt, ...);
+
+namespace cc {
+
+struct Tuning {
+  int mode = 0;             // CC_OPT_UPDATE_MODE
+  int block = 256;          // CC_OPT_BLOCK
+  int items = 0;            // CC_OPT_ITEMS (0 = per call)
+  int query_halving = 1;    // CC_OPT_QUERY_HALVING
+  int64_t compress_every = 0;  // CC_OPT_COMPRESS_EVERY
+  int hook = 0;             // CC_OPT_HOOK
+  int grid_cap = 4096;      // CC_OPT_GRID_CAP
+  int compress_linked = 1;  // CC_OPT_COMPRESS_LINKED
+};
+
+inline bool set_tuning(Tuning* t, int key, int64_t v) {
+  switch (key) {
+    case CC_OPT_UPDATE_MODE:
+      if (v != 0 && v != 1) return false;
+      t->mode = (int)v;
+      return true;
+    case CC_OPT_BLOCK:
+      if (v < 64 || v > 1024 || v % 64) return false;
+      t->block = (int)v;
+      return true;
+    case CC_OPT_ITEMS:
+      if (v != 0 && v != 1 && v != 2 && v != 4 && v != 8) return false;
+      t->items = (int)v;
+      return true;
+    case CC_OPT_QUERY_HALVING:
+      if (v != 0 && v != 1) return false;
+      t->query_halving = (int)v;
+      return true;
+    case CC_OPT_COMPRESS_EVERY:
+      if (v < 0) return false;
+      t->compress_every = v;
+      return true;
+    case CC_OPT_HOOK:
+      if (v != 0 && v != 1) return false;
+      t->hook = (int)v;
+      return true;
+    case CC_OPT_GRID_CAP:
+      if (v < 1 || v > (1 << 20)) return false;
+      t->grid_cap = (int)v;
+      return true;
+    case CC_OPT_COMPRESS_LINKED:
+      if (v != 0 && v != 1) return false;
+      t->compress_linked = (int)v;
+      return true;
+    default:
+      return false;
+  }
+}
+
+inline bool get_tuning(const Tuning* t, int key, int64_t* v) {
+  switch (key) {
+    case CC_OPT_UPDATE_MODE: *v = t->mode; return true;
+    case CC_OPT_BLOCK: *v = t->block; return true;
+    case CC_OPT_ITEMS: *v = t->items; return true;
+    case CC_OPT_QUERY_HALVING: *v = t->query_halving; return true;
+    case CC_OPT_COMPRESS_EVERY: *v = t->compress_every; return true;
+    case CC_OPT_HOOK: *v = t->hook; return true;
+    case CC_OPT_GRID_CAP: *v = t->grid_cap; return true;
+    case CC_OPT_COMPRESS_LINKED: *v = t->compress_linked; return true;
+    default: return false;
+  }
+}
+
+// Items per thread for a launch over m items: the requested value, or with
+// 0 the largest of 8, 4, 2, 1 that still gives at least 2048 blocks.
+inline int pick_items(int requested, int64_t m, int block) {
+  if (requested > 0) return requested;
+  int it = 8;
+  while (it > 1 && m < (int64_t)block * it * 2048) it >>= 1;
+  return it;
+}
+
+inline uint32_t fmix32_host(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x85ebca6bu;
+  h ^= h >> 13;
+  h *= 0xc2b2ae35u;
+  h ^= h >> 16;
+  return h;
+}
+
+// A parent image is a valid forest under the linking order when every
+// pointer stays in range and goes from lower to strictly higher priority
+// (then no cycle is possible).  Counts the roots.
+inline bool check_forest(const int32_t* p, int64_t n, int hook, int64_t* roots) {
+  int64_t r = 0;
+  for (int64_t v = 0; v < n; ++v) {
+    const int32_t q = p[v];
+    if (q < 0 || q >= n) return false;
+    if (q == v) {
+      ++r;
+      continue;
+    }
+    const bool ok = hook == 1 ? fmix32_host((uint32_t)q) < fmix32_host((uint32_t)v) : q < v;
+    if (!ok) return false;
+  }
+  *roots = r;
+  return true;
+}
+
+}  // namespace cc

@@ -1,0 +1,443 @@
+// C ABI of the plain path (include/cc.h): one graph, one launch set per bulk
+// operation, all work stream ordered on the graph's HIP stream.
+#include <hip/hip_runtime.h>
+
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "../../include/cc.h"
+#include "cc_kernels.hpp"
+#include "cc_internal.hpp"
+
+using namespace ccdev;
+
+namespace {
+thread_local char g_err[512] = "";
+}
+
+void cc_set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+extern "C" const char* cc_last_error(void) { return g_err; }
+
+extern "C" const char* cc_strerror(int code) {
+  switch (code) {
+    case CC_OK: return "ok";
+    case CC_EINVAL: return "invalid argument";
+    case CC_ENOMEM: return "out of memory";
+    case CC_ERANGE: return "vertex id out of range (item skipped)";
+    case CC_EDEVICE: return "HIP device error";
+    case CC_ECORRUPT: return "corrupt union-find forest";
+    default: return "unknown status";
+  }
+}
+
+#define HIP_TRY(expr)                                                               \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess) {                                                         \
+      cc_set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                   __LINE__);                                                       \
+      return CC_EDEVICE;                                                            \
+    }                                                                               \
+  } while (0)
+
+struct cc_graph {
+  int64_t n = 0;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int32_t* parent = nullptr;
+  unsigned long long* slots = nullptr;  // kSlots spread link counters
+  unsigned long long* red = nullptr;    // reduction result (count_roots)
+  int* flags = nullptr;
+  int2* live = nullptr;
+  unsigned* live_ctl = nullptr;  // [0] live count, [1] finished blocks, [2..3] same for hooked
+  int32_t* hooked = nullptr;     // roots linked by the last fused update (n entries)
+  int64_t live_cap = 0;
+  int64_t updates = 0;
+  cc::Tuning tune;
+};
+
+namespace {
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+    else prev = -1;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) hipSetDevice(prev);
+  }
+};
+
+int alloc_live(cc_graph* g, int64_t cap) {
+  if (cap <= g->live_cap) return CC_OK;
+  if (g->live) {
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    HIP_TRY(hipFree(g->live));
+    g->live = nullptr;
+    g->live_cap = 0;
+  }
+  if (hipMalloc(&g->live, (size_t)cap * sizeof(int2)) != hipSuccess) {
+    g->live = nullptr;
+    cc_set_error("hipMalloc of %lld live pairs failed", (long long)cap);
+    return CC_ENOMEM;
+  }
+  g->live_cap = cap;
+  return CC_OK;
+}
+
+int alloc_hooked(cc_graph* g) {
+  if (g->hooked) return CC_OK;
+  if (hipMalloc(&g->hooked, (size_t)g->n * sizeof(int32_t)) != hipSuccess) {
+    g->hooked = nullptr;
+    cc_set_error("hipMalloc of %lld hooked entries failed", (long long)g->n);
+    return CC_ENOMEM;
+  }
+  return CC_OK;
+}
+
+inline unsigned blocks_for(int64_t items, int64_t per_block, int cap) {
+  int64_t b = (items + per_block - 1) / per_block;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return (unsigned)b;
+}
+
+int launch_init(cc_graph* g) {
+  const unsigned blocks = blocks_for((g->n + 3) / 4, 256, 2048);
+  hipLaunchKernelGGL(k_init, dim3(blocks), dim3(256), 0, g->stream, g->parent, g->n);
+  hipLaunchKernelGGL(k_zero_u64, dim3(4), dim3(256), 0, g->stream, g->slots, kSlots * kSlotStride);
+  HIP_TRY(hipGetLastError());
+  return CC_OK;
+}
+
+template <int ITEMS, class Ord, bool RECORD>
+void launch_fused_t(cc_graph* g, const int2* e, int64_t m) {
+  const int B = g->tune.block;
+  const unsigned blocks = blocks_for(m, (int64_t)B * ITEMS, g->tune.grid_cap);
+  hipLaunchKernelGGL((k_update_fused<ITEMS, Ord, RECORD>), dim3(blocks), dim3(B), 0, g->stream, g->parent, e,
+                     m, (int32_t)g->n, g->slots, g->flags, g->hooked, g->live_ctl + 2);
+}
+
+template <class Ord, bool RECORD>
+void launch_fused_r(cc_graph* g, const int2* e, int64_t m) {
+  switch (cc::pick_items(g->tune.items, m, g->tune.block)) {
+    case 1: launch_fused_t<1, Ord, RECORD>(g, e, m); break;
+    case 2: launch_fused_t<2, Ord, RECORD>(g, e, m); break;
+    case 8: launch_fused_t<8, Ord, RECORD>(g, e, m); break;
+    default: launch_fused_t<4, Ord, RECORD>(g, e, m); break;
+  }
+}
+
+template <class Ord>
+void launch_fused_o(cc_graph* g, const int2* e, int64_t m) {
+  if (g->tune.compress_linked) {
+    launch_fused_r<Ord, true>(g, e, m);
+    const unsigned blocks = blocks_for(std::min<int64_t>(m, g->n), 256, 1024);
+    hipLaunchKernelGGL(k_compress_hooked, dim3(blocks), dim3(256), 0, g->stream, g->parent, g->hooked,
+                       g->live_ctl + 2, (int32_t)g->n, g->flags);
+  } else {
+    launch_fused_r<Ord, false>(g, e, m);
+  }
+}
+
+template <int ITEMS>
+void launch_filter_t(cc_graph* g, const int2* e, int64_t m) {
+  const int B = g->tune.block;
+  const unsigned blocks = blocks_for(m, (int64_t)B * ITEMS, g->tune.grid_cap);
+  hipLaunchKernelGGL((k_filter<ITEMS>), dim3(blocks), dim3(B), (size_t)B * ITEMS * sizeof(int2), g->stream,
+                     g->parent, e, m, (int32_t)g->n, g->live, g->live_ctl, g->flags);
+}
+
+template <class Ord>
+void launch_split_o(cc_graph* g, const int2* e, int64_t m) {
+  switch (cc::pick_items(g->tune.items, m, g->tune.block)) {
+    case 1: launch_filter_t<1>(g, e, m); break;
+    case 2: launch_filter_t<2>(g, e, m); break;
+    case 8: launch_filter_t<8>(g, e, m); break;
+    default: launch_filter_t<4>(g, e, m); break;
+  }
+  const int B = g->tune.block;
+  const unsigned blocks = blocks_for(m, B, g->tune.grid_cap);
+  hipLaunchKernelGGL((k_link_live<Ord>), dim3(blocks), dim3(B), 0, g->stream, g->parent, g->live,
+                     g->live_ctl, (int32_t)g->n, g->slots, g->flags);
+  hipLaunchKernelGGL(k_compress_live, dim3(blocks), dim3(B), 0, g->stream, g->parent, g->live, g->live_ctl,
+                     (int32_t)g->n, g->flags);
+}
+
+template <int ITEMS, bool HALVE>
+void launch_query_t(cc_graph* g, const int2* p, int64_t q, uint8_t* out) {
+  const int B = g->tune.block;
+  const unsigned blocks = blocks_for(q, (int64_t)B * ITEMS, g->tune.grid_cap);
+  hipLaunchKernelGGL((k_query<ITEMS, HALVE>), dim3(blocks), dim3(B), 0, g->stream, g->parent, p, q,
+                     (int32_t)g->n, out, g->flags);
+}
+
+template <bool HALVE>
+void launch_query_h(cc_graph* g, const int2* p, int64_t q, uint8_t* out) {
+  switch (cc::pick_items(g->tune.items, q, g->tune.block)) {
+    case 1: launch_query_t<1, HALVE>(g, p, q, out); break;
+    case 2: launch_query_t<2, HALVE>(g, p, q, out); break;
+    case 8: launch_query_t<8, HALVE>(g, p, q, out); break;
+    default: launch_query_t<4, HALVE>(g, p, q, out); break;
+  }
+}
+
+unsigned vertex_blocks(const cc_graph* g) { return blocks_for(g->n, 256, 4096); }
+
+int read_links(cc_graph* g, unsigned long long* links) {
+  std::vector<unsigned long long> h((size_t)kSlots * kSlotStride);
+  HIP_TRY(hipMemcpyAsync(h.data(), g->slots, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                         g->stream));
+  HIP_TRY(hipStreamSynchronize(g->stream));
+  unsigned long long s = 0;
+  for (int i = 0; i < kSlots; ++i) s += h[(size_t)i * kSlotStride];
+  *links = s;
+  return CC_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+
+extern "C" cc_graph* cc_create(int64_t n) {
+  if (n < 1 || n > 0x7fffffffLL) {
+    cc_set_error("cc_create: n=%lld outside [1, 2^31-1]", (long long)n);
+    return nullptr;
+  }
+  cc_graph* g = new (std::nothrow) cc_graph();
+  if (!g) {
+    cc_set_error("cc_create: host allocation failed");
+    return nullptr;
+  }
+  g->n = n;
+  auto fail = [&](const char* what, hipError_t e) -> cc_graph* {
+    cc_set_error("cc_create: %s: %s", what, hipGetErrorString(e));
+    (void)hipFree(g->parent);
+    (void)hipFree(g->slots);
+    (void)hipFree(g->red);
+    (void)hipFree(g->flags);
+    (void)hipFree(g->live_ctl);
+    delete g;
+    return nullptr;
+  };
+  hipError_t e;
+  if ((e = hipGetDevice(&g->device)) != hipSuccess) return fail("hipGetDevice", e);
+  if ((e = hipMalloc(&g->parent, (size_t)n * sizeof(int32_t))) != hipSuccess) return fail("parent", e);
+  if ((e = hipMalloc(&g->slots, (size_t)kSlots * kSlotStride * 8)) != hipSuccess) return fail("slots", e);
+  if ((e = hipMalloc(&g->red, 64)) != hipSuccess) return fail("red", e);
+  if ((e = hipMalloc(&g->flags, 64)) != hipSuccess) return fail("flags", e);
+  if ((e = hipMalloc(&g->live_ctl, 64)) != hipSuccess) return fail("live_ctl", e);
+  if ((e = hipMemsetAsync(g->flags, 0, 64, g->stream)) != hipSuccess) return fail("memset", e);
+  if ((e = hipMemsetAsync(g->live_ctl, 0, 64, g->stream)) != hipSuccess) return fail("memset", e);
+  if (launch_init(g) != CC_OK) return fail("init launch", hipGetLastError());
+  if ((e = hipStreamSynchronize(g->stream)) != hipSuccess) return fail("sync", e);
+  return g;
+}
+
+extern "C" int cc_destroy(cc_graph* g) {
+  if (!g) return CC_EINVAL;
+  DeviceGuard dg(g->device);
+  (void)hipStreamSynchronize(g->stream);
+  (void)hipFree(g->parent);
+  (void)hipFree(g->slots);
+  (void)hipFree(g->red);
+  (void)hipFree(g->flags);
+  (void)hipFree(g->live);
+  (void)hipFree(g->live_ctl);
+  delete g;
+  return CC_OK;
+}
+
+extern "C" int cc_set_stream(cc_graph* g, void* stream) {
+  if (!g) return CC_EINVAL;
+  g->stream = (hipStream_t)stream;
+  return CC_OK;
+}
+
+extern "C" int cc_set_option(cc_graph* g, int key, int64_t value) {
+  if (!g) return CC_EINVAL;
+  if (!cc::set_tuning(&g->tune, key, value)) {
+    cc_set_error("cc_set_option: key %d value %lld rejected", key, (long long)value);
+    return CC_EINVAL;
+  }
+  return CC_OK;
+}
+
+extern "C" int cc_get_option(cc_graph* g, int key, int64_t* value) {
+  if (!g || !value) return CC_EINVAL;
+  if (!cc::get_tuning(&g->tune, key, value)) return CC_EINVAL;
+  return CC_OK;
+}
+
+extern "C" int cc_reserve(cc_graph* g, int64_t max_batch) {
+  if (!g || max_batch < 0) return CC_EINVAL;
+  DeviceGuard dg(g->device);
+  int rc = alloc_hooked(g);
+  if (rc != CC_OK) return rc;
+  return alloc_live(g, max_batch);
+}
+
+extern "C" int cc_reset(cc_graph* g) {
+  if (!g) return CC_EINVAL;
+  DeviceGuard dg(g->device);
+  g->updates = 0;
+  return launch_init(g);
+}
+
+extern "C" int cc_bulk_update(cc_graph* g, const int32_t* edges, int64_t m) {
+  if (!g || m < 0 || (m > 0 && !edges)) {
+    cc_set_error("cc_bulk_update: invalid argument");
+    return CC_EINVAL;
+  }
+  if (m == 0) return CC_OK;
+  DeviceGuard dg(g->device);
+  const int2* e = reinterpret_cast<const int2*>(edges);
+  const bool hashed = g->tune.hook == 1;
+  if (g->tune.mode == 1) {
+    int rc = alloc_live(g, m);
+    if (rc != CC_OK) return rc;
+    if (hashed) launch_split_o<ByHash>(g, e, m);
+    else launch_split_o<ById>(g, e, m);
+  } else {
+    if (g->tune.compress_linked) {
+      int rc = alloc_hooked(g);
+      if (rc != CC_OK) return rc;
+    }
+    if (hashed) launch_fused_o<ByHash>(g, e, m);
+    else launch_fused_o<ById>(g, e, m);
+  }
+  g->updates++;
+  if (g->tune.compress_every > 0 && g->updates % g->tune.compress_every == 0)
+    hipLaunchKernelGGL(k_compress_all, dim3(vertex_blocks(g)), dim3(256), 0, g->stream, g->parent,
+                       (int32_t)g->n, g->flags);
+  HIP_TRY(hipGetLastError());
+  return CC_OK;
+}
+
+extern "C" int cc_bulk_query(cc_graph* g, const int32_t* pairs, int64_t q, uint8_t* out) {
+  if (!g || q < 0 || (q > 0 && (!pairs || !out))) {
+    cc_set_error("cc_bulk_query: invalid argument");
+    return CC_EINVAL;
+  }
+  if (q == 0) return CC_OK;
+  DeviceGuard dg(g->device);
+  const int2* p = reinterpret_cast<const int2*>(pairs);
+  if (g->tune.query_halving) launch_query_h<true>(g, p, q, out);
+  else launch_query_h<false>(g, p, q, out);
+  HIP_TRY(hipGetLastError());
+  return CC_OK;
+}
+
+extern "C" int cc_labels(cc_graph* g, int32_t* out) {
+  if (!g || !out) return CC_EINVAL;
+  DeviceGuard dg(g->device);
+  const unsigned blocks = vertex_blocks(g);
+  const int32_t n = (int32_t)g->n;
+  if (g->tune.hook == 1) {
+    hipLaunchKernelGGL(k_fill_i32, dim3(blocks), dim3(256), 0, g->stream, out, n, n);
+    hipLaunchKernelGGL(k_labels_min, dim3(blocks), dim3(256), 0, g->stream, g->parent, n, out, g->flags);
+    hipLaunchKernelGGL(k_labels_gather, dim3(blocks), dim3(256), 0, g->stream, g->parent, n, out, g->flags);
+  } else {
+    hipLaunchKernelGGL(k_labels_id, dim3(blocks), dim3(256), 0, g->stream, g->parent, n, out, g->flags);
+  }
+  HIP_TRY(hipGetLastError());
+  return CC_OK;
+}
+
+extern "C" int cc_num_components(cc_graph* g, int64_t* out) {
+  if (!g || !out) return CC_EINVAL;
+  DeviceGuard dg(g->device);
+  unsigned long long links = 0;
+  int rc = read_links(g, &links);
+  if (rc != CC_OK) return rc;
+  *out = g->n - (int64_t)links;
+  return CC_OK;
+}
+
+extern "C" int cc_count_roots(cc_graph* g, int64_t* out) {
+  if (!g || !out) return CC_EINVAL;
+  DeviceGuard dg(g->device);
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, g->stream, g->red, 1);
+  hipLaunchKernelGGL(k_count_roots, dim3(vertex_blocks(g)), dim3(256), 0, g->stream, g->parent,
+                     (int32_t)g->n, g->red);
+  HIP_TRY(hipGetLastError());
+  unsigned long long h = 0;
+  HIP_TRY(hipMemcpyAsync(&h, g->red, 8, hipMemcpyDeviceToHost, g->stream));
+  HIP_TRY(hipStreamSynchronize(g->stream));
+  *out = (int64_t)h;
+  return CC_OK;
+}
+
+extern "C" int cc_sync(cc_graph* g) {
+  if (!g) return CC_EINVAL;
+  DeviceGuard dg(g->device);
+  HIP_TRY(hipStreamSynchronize(g->stream));
+  int f = 0;
+  HIP_TRY(hipMemcpyAsync(&f, g->flags, sizeof(int), hipMemcpyDeviceToHost, g->stream));
+  HIP_TRY(hipStreamSynchronize(g->stream));
+  if (f) {
+    HIP_TRY(hipMemsetAsync(g->flags, 0, sizeof(int), g->stream));
+    HIP_TRY(hipStreamSynchronize(g->stream));
+  }
+  if (f & kFlagCorrupt) {
+    cc_set_error("a find exceeded n steps: the forest holds a cycle");
+    return CC_ECORRUPT;
+  }
+  if (f & kFlagRange) {
+    cc_set_error("an edge or pair held a vertex id outside [0, n); it was skipped");
+    return CC_ERANGE;
+  }
+  return CC_OK;
+}
+
+extern "C" int64_t cc_num_vertices(const cc_graph* g) { return g ? g->n : 0; }
+
+extern "C" int64_t cc_state_bytes(const cc_graph* g) { return g ? 16 + 4 * g->n : 0; }
+
+extern "C" int cc_save(cc_graph* g, void* host_buf) {
+  if (!g || !host_buf) return CC_EINVAL;
+  DeviceGuard dg(g->device);
+  unsigned long long links = 0;
+  int rc = read_links(g, &links);
+  if (rc != CC_OK) return rc;
+  int64_t hdr[2] = {g->n, (int64_t)links};
+  memcpy(host_buf, hdr, 16);
+  HIP_TRY(hipMemcpyAsync((char*)host_buf + 16, g->parent, (size_t)g->n * 4, hipMemcpyDeviceToHost, g->stream));
+  HIP_TRY(hipStreamSynchronize(g->stream));
+  return CC_OK;
+}
+
+extern "C" int cc_load(cc_graph* g, const void* host_buf) {
+  if (!g || !host_buf) return CC_EINVAL;
+  DeviceGuard dg(g->device);
+  int64_t hdr[2];
+  memcpy(hdr, host_buf, 16);
+  if (hdr[0] != g->n) {
+    cc_set_error("cc_load: image has n=%lld, graph has n=%lld", (long long)hdr[0], (long long)g->n);
+    return CC_EINVAL;
+  }
+  const int32_t* p = reinterpret_cast<const int32_t*>((const char*)host_buf + 16);
+  int64_t roots = 0;
+  if (!cc::check_forest(p, g->n, g->tune.hook, &roots) || hdr[1] != g->n - roots) {
+    cc_set_error("cc_load: image is not a forest under the graph's linking order");
+    return CC_ECORRUPT;
+  }
+  std::vector<unsigned long long> h((size_t)kSlots * kSlotStride, 0ull);
+  h[0] = (unsigned long long)hdr[1];
+  HIP_TRY(hipStreamSynchronize(g->stream));
+  HIP_TRY(hipMemcpyAsync(g->parent, p, (size_t)g->n * 4, hipMemcpyHostToDevice, g->stream));
+  HIP_TRY(hipMemcpyAsync(g->slots, h.data(), h.size() * 8, hipMemcpyHostToDevice, g->stream));
+  HIP_TRY(hipStreamSynchronize(g->stream));
+  return CC_OK;
+}

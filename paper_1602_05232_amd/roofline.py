@@ -1,0 +1,71 @@
+"""Measured roofline denominators for the connectivity kernels.
+
+Thin wrappers over include/cc_bench.h, timed with HIP events on the current
+torch stream:
+  G(N)  random 4-byte gathers per second from an N-entry int32 table,
+  B_s   streaming read bandwidth (bytes/s),
+  C     random device-scope compare-and-swaps per second.
+The per-edge Bulk-Update bound is E_roof = 1 / (2/G + 8/B_s): two random
+parent reads (one find per endpoint at depth one) plus 8 streamed bytes.
+"""
+from __future__ import annotations
+
+import torch
+
+from .cc import lib, stream_handle
+
+
+def _time(fn, reps=3):
+    s = torch.cuda.current_stream()
+    best = None
+    for _ in range(reps + 1):  # first call warms up
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(s)
+        fn()
+        b.record(s)
+        b.synchronize()
+        t = a.elapsed_time(b) / 1e3
+        best = t if best is None else min(best, t)
+    return best
+
+
+def gather_rate(n_table: int, count: int = 1 << 28, table: torch.Tensor | None = None) -> float:
+    """Random 4-byte gathers per second from an n_table-entry table."""
+    t = table if table is not None else torch.arange(n_table, dtype=torch.int32, device="cuda")
+    sink = torch.zeros(1, dtype=torch.int32, device="cuda")
+    h = stream_handle(None)
+
+    def run():
+        rc = lib().ccb_gather(t.data_ptr(), n_table, count, 0x1234567, sink.data_ptr(), h)
+        assert rc == 0, rc
+    return count / _time(run)
+
+
+def stream_bandwidth(nbytes: int = 1 << 31) -> float:
+    buf = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+    sink = torch.zeros(1, dtype=torch.int32, device="cuda")
+    h = stream_handle(None)
+
+    def run():
+        assert lib().ccb_stream_read(buf.data_ptr(), nbytes, sink.data_ptr(), h) == 0
+    t = _time(run)
+    del buf
+    return nbytes / t
+
+
+def cas_rate(n_table: int, count: int = 1 << 26) -> float:
+    t = torch.arange(n_table, dtype=torch.int32, device="cuda")
+    h = stream_handle(None)
+
+    def run():
+        assert lib().ccb_cas(t.data_ptr(), n_table, count, 0x7654321, h) == 0
+    return count / _time(run)
+
+
+def copy_bytes(dst: torch.Tensor, src: torch.Tensor, nbytes: int):
+    assert lib().ccb_copy(dst.data_ptr(), src.data_ptr(), nbytes, stream_handle(None)) == 0
+
+
+def edge_roofline(G: float, Bs: float) -> float:
+    """Bulk-Update edges/s bound: 2 random parent reads + 8 streamed bytes per edge."""
+    return 1.0 / (2.0 / G + 8.0 / Bs)

@@ -1,0 +1,238 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bit-exact on every query answer byte, every min-id label and the component
+count, after every minibatch unless stated otherwise.  Inputs come from the
+seeded generators; expected values only from the oracle.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+OPTION_SETS = [
+    dict(update_mode=0, hook=0),
+    dict(update_mode=1, hook=0),
+    dict(update_mode=0, hook=1),
+    dict(update_mode=1, hook=1),
+    dict(update_mode=0, block=64, items=1, grid_cap=7, compress_linked=0),
+    dict(update_mode=1, block=1024, items=8, grid_cap=3),
+    dict(update_mode=0, query_halving=0, compress_every=3, items=2, compress_linked=0),
+    dict(update_mode=0, hook=1, items=8, block=512, grid_cap=5),
+]
+
+
+def opt_id(o):
+    return ",".join("%s=%s" % kv for kv in sorted(o.items()))
+
+
+@pytest.fixture(scope="module")
+def cc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1602_05232_amd as ccgpu  # raises if libcc.so is missing
+    ccgpu.lib()
+    return ccgpu
+
+
+def dev(a):
+    a = np.asarray(a)
+    if a.dtype != np.int32:
+        a = a.astype(np.int32)
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def run_parity(cc, s, opts, label_every=1, check_roots=True):
+    """Stream s through the GPU graph and the oracle side by side."""
+    print("parity: %s n=%d batches=%d opts=%s" % (s.name, s.n, s.num_batches, opts), flush=True)
+    ref = oracle.UnionFind(s.n)
+    g = cc.Graph(s.n, **opts)
+    edges, queries = dev(s.edges), dev(s.queries)
+    probes = dev(s.probes) if len(s.probes) else None
+    out = torch.empty(len(s.queries), dtype=torch.uint8, device="cuda")
+    want = np.empty(len(s.queries), np.uint8)
+    prev = np.zeros(len(s.probes), np.uint8)
+    nb = s.num_batches
+    for i in range(nb):
+        e0, e1 = int(s.eoff[i]), int(s.eoff[i + 1])
+        q0, q1 = int(s.qoff[i]), int(s.qoff[i + 1])
+        ref.bulk_update(s.edges[e0:e1])
+        g.bulk_update(edges[e0:e1])
+        want[q0:q1] = ref.bulk_query(s.queries[q0:q1])
+        g.bulk_query(queries[q0:q1], out=out[q0:q1])
+        if probes is not None:
+            pa = g.bulk_query(probes).cpu().numpy()
+            np.testing.assert_array_equal(pa, ref.bulk_query(s.probes))
+            assert (pa >= prev).all()
+            prev = pa
+        if (label_every and i % label_every == 0) or i == nb - 1:
+            lab = g.labels().cpu().numpy()
+            np.testing.assert_array_equal(lab, ref.labels(), err_msg="labels after minibatch %d" % i)
+            assert g.num_components() == ref.num_components()
+            if check_roots:
+                assert g.count_roots() == ref.num_components()
+    np.testing.assert_array_equal(out.cpu().numpy(), want)
+    assert g.sync() == cc.cc.CC_OK
+    g.close()
+    return ref
+
+
+@pytest.mark.parametrize("opts", OPTION_SETS, ids=opt_id)
+def test_er_tiny(cc, opts):
+    run_parity(cc, synth.er_stream(), opts)
+
+
+@pytest.mark.parametrize("opts", OPTION_SETS, ids=opt_id)
+def test_rmat_small(cc, opts):
+    run_parity(cc, synth.rmat_stream(scale=16, size_lo=8, size_hi=16, qbatch=1 << 12), opts)
+
+
+@pytest.mark.parametrize("opts", OPTION_SETS[:4], ids=opt_id)
+def test_grid_small(cc, opts):
+    s = synth.grid_stream_cfg(W=256, H=256, batch=1 << 12, qbatch=1 << 10)
+    ref = run_parity(cc, s, opts, label_every=4)
+    assert ref.num_components() >= 1
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_ragged_sizes(cc, mode):
+    sizes = [1, 63, 64, 65, 255, 257, 1023, 1025, 4095, 4097, 0, 3, 12289]
+    n = 5000
+    m = sum(sizes)
+    e = synth.uniform_pairs(synth.key(11, 0, 1), 0, m, n)
+    q = synth.uniform_pairs(synth.key(11, 0, 2), 0, 997 * len(sizes), n)
+    s = synth.Stream("ragged", n, e, synth._offsets(sizes), q, synth._offsets([997] * len(sizes)))
+    run_parity(cc, s, dict(update_mode=mode, items=4, block=256))
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_edge_cases(cc, mode):
+    n = 1 << 12
+    g = cc.Graph(n, update_mode=mode)
+    ref = oracle.UnionFind(n)
+
+    def both(e):
+        e = np.asarray(e, np.int32).reshape(-1, 2)
+        ref.bulk_update(e)
+        g.bulk_update(dev(e))
+
+    both(np.empty((0, 2)))  # empty minibatch
+    both(np.stack([np.arange(n), np.arange(n)], 1))  # all self-loops
+    assert g.num_components() == n
+    both(np.tile([[5, 9]], (1 << 16, 1)))  # one edge repeated
+    assert g.num_components() == n - 1
+    star = [(100, 100 + k) for k in range(1, 8)]  # the Section 4.2 star
+    both(star)
+    lab = g.labels().cpu().numpy()
+    np.testing.assert_array_equal(lab, ref.labels())
+    assert (lab[100:108] == 100).all()
+    assert g.sync() == cc.cc.CC_OK
+    # (u, u) queries answer 1 even for isolated vertices
+    a = g.bulk_query(dev([[7, 7], [4000, 4000], [5, 9], [9, 5], [5, 6]])).cpu().numpy()
+    np.testing.assert_array_equal(a, [1, 1, 1, 1, 0])
+    g.close()
+
+
+@pytest.mark.parametrize("opts", [dict(update_mode=0), dict(update_mode=1), dict(update_mode=0, hook=1)],
+                         ids=opt_id)
+def test_deep_chain(cc, opts):
+    # reversed path in one minibatch, then in single-edge minibatches
+    n = 1 << 20
+    i = np.arange(n - 2, -1, -1, dtype=np.int32)
+    g = cc.Graph(n, **opts)
+    g.bulk_update(dev(np.stack([i, i + 1], 1)))
+    assert g.num_components() == 1
+    assert (g.labels().cpu().numpy() == 0).all()
+    g.close()
+    n = 1 << 12
+    g = cc.Graph(n, **opts)
+    i = np.arange(n - 2, -1, -1, dtype=np.int32)
+    e = dev(np.stack([i + 1, i], 1))
+    for k in range(n - 1):
+        g.bulk_update(e[k:k + 1])
+    assert g.num_components() == 1
+    q = dev(np.stack([np.zeros(n, np.int32), np.arange(n, dtype=np.int32)], 1))
+    assert g.bulk_query(q).cpu().numpy().all()
+    assert g.sync() == cc.cc.CC_OK
+    g.close()
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_invalid_ids(cc, mode):
+    n = 10
+    g = cc.Graph(n, update_mode=mode)
+    ref = oracle.UnionFind(n)
+    e = np.array([(0, 1), (-1, 2), (2, 10), (3, 4), (11, -5), (4, 5)], np.int32)
+    ref.bulk_update(e)
+    g.bulk_update(dev(e))
+    assert g.sync() == cc.cc.CC_ERANGE
+    assert g.sync() == cc.cc.CC_OK  # reported once
+    assert g.num_components() == ref.num_components() == n - 3
+    p = np.array([(0, 1), (3, 5), (0, 10), (-1, -1), (7, 7), (1, 3)], np.int32)
+    np.testing.assert_array_equal(g.bulk_query(dev(p)).cpu().numpy(), ref.bulk_query(p))
+    assert g.sync() == cc.cc.CC_ERANGE
+    np.testing.assert_array_equal(g.labels().cpu().numpy(), ref.labels())
+    g.close()
+
+
+def test_argument_errors(cc):
+    g = cc.Graph(16)
+    L = cc.lib()
+    assert L.cc_bulk_update(g.handle, None, 3) == cc.cc.CC_EINVAL
+    assert L.cc_bulk_update(g.handle, None, -1) == cc.cc.CC_EINVAL
+    assert L.cc_bulk_query(g.handle, None, 2, None) == cc.cc.CC_EINVAL
+    assert L.cc_set_option(g.handle, 2, 100) == cc.cc.CC_EINVAL
+    assert L.cc_set_option(g.handle, 99, 1) == cc.cc.CC_EINVAL
+    assert g.sync() == cc.cc.CC_OK
+    g.close()
+
+
+@pytest.mark.parametrize("hook", [0, 1])
+def test_save_load_resume(cc, hook):
+    s = synth.rmat_stream(scale=14, size_lo=8, size_hi=13, qbatch=256)
+    half = s.num_batches // 2
+    a = cc.Graph(s.n, hook=hook)
+    for i in range(half):
+        a.bulk_update(dev(s.batch(i)))
+    img = a.save()
+    b = cc.Graph(s.n, hook=hook, update_mode=1)
+    b.load(img)
+    assert b.num_components() == a.num_components()
+    for i in range(half, s.num_batches):
+        a.bulk_update(dev(s.batch(i)))
+        b.bulk_update(dev(s.batch(i)))
+    np.testing.assert_array_equal(a.labels().cpu().numpy(), b.labels().cpu().numpy())
+    ref = oracle.UnionFind(s.n)
+    ref.bulk_update(s.edges)
+    np.testing.assert_array_equal(b.labels().cpu().numpy(), ref.labels())
+    # a cycle in the image is rejected and leaves the graph unchanged
+    bad = bytearray(img)
+    par = np.frombuffer(bad, np.int32, offset=16)
+    par[3], par[4] = 4, 3
+    before = b.labels().cpu().numpy()
+    with pytest.raises(cc.CCError) as ei:
+        b.load(bad)
+    assert ei.value.code == cc.cc.CC_ECORRUPT
+    np.testing.assert_array_equal(b.labels().cpu().numpy(), before)
+    a.close()
+    b.close()
+
+
+def test_order_independence_and_reset(cc):
+    s = synth.rmat_stream(scale=15, size_lo=10, size_hi=15, qbatch=16)
+    rng = np.random.default_rng(3)
+    g = cc.Graph(s.n)
+    g.bulk_update(dev(s.edges))
+    want = g.labels().cpu().numpy()
+    for mode in (0, 1):
+        g.set_option("update_mode", mode)
+        g.reset()
+        assert g.num_components() == s.n
+        e = s.edges[rng.permutation(len(s.edges))][:, ::-1]
+        for b in np.array_split(e, 5):
+            g.bulk_update(dev(b))
+        np.testing.assert_array_equal(g.labels().cpu().numpy(), want)
+    g.close()
