@@ -1,19 +1,24 @@
 #!/usr/bin/env python3
 """Throughput benchmark of the bulk incremental connectivity hot path.
 
-One step = one pass of the whole path over the R-MAT scale-24 stream
-(n = 2^24 vertices, 2^28 edges with a=.57 b=.19 c=.19 d=.05 and randomly
-permuted ids, streamed as minibatches of log-uniform size in [2^16, 2^24],
-each followed by a Bulk-Query of 2^20 uniform random pairs): reset the forest,
-then every Bulk-Update and Bulk-Query in stream order, then the min-id label
-pass and the component count.  Inputs are generated on the host and resident
-in HBM before timing starts.
+Default workload (`--workload rmat24`, the headline configuration): one step
+is one pass of the whole path over the R-MAT scale-24 stream (n = 2^24
+vertices, 2^28 edges with a=.57 b=.19 c=.19 d=.05 and randomly permuted ids,
+streamed as minibatches of log-uniform size in [2^16, 2^24], each followed by
+a Bulk-Query of 2^20 uniform random pairs): reset the forest, every
+Bulk-Update and Bulk-Query in stream order, then the min-id label pass and the
+component count.  Inputs are generated on the host and resident in HBM before
+timing starts.
+
+Other workloads compare the forms of the path on their own configurations:
+  grid4096     4096^2 mesh + 1% long-range edges, 2^12-edge minibatches each
+               followed by 2^10 queries: plain launches vs one HIP-graph replay
+  batched1024  1024 independent graphs (log-normal sizes): one launch per
+               graph and operation vs the pool's one launch per round
+  serve64      see serve.py (request loop over 64 R-MAT scale-22 graphs)
 
 Prints ONE JSON line.  `value` is (update edges + query pairs) per second of
-wall clock over the timed steps; the per-operation rates come from HIP events
-on the graph's stream.  Also reported: the update kernel against the HBM
-roofline (algorithmic bytes), against a measured random-gather roofline, and
-the CPU oracle's rate on a bounded sample of the same stream.
+wall clock over the timed steps.
 """
 from __future__ import annotations
 
@@ -75,54 +80,47 @@ def pct(xs, p):
     return xs[k]
 
 
-def cpu_baseline(s, budget_s: float):
-    """The oracle, as it is, on a prefix of the same stream (one thread)."""
+def cpu_baseline(streams, budget_s: float):
+    """The oracle, as it is, on a prefix of the same work (one thread)."""
     import oracle
-    uf = oracle.UnionFind(s.n)
     edges = queries = 0
     t0 = time.perf_counter()
-    nb = 0
-    for i in range(s.num_batches):
-        uf.bulk_update(s.batch(i))
-        uf.bulk_query(s.query(i))
-        edges += int(s.eoff[i + 1] - s.eoff[i])
-        queries += int(s.qoff[i + 1] - s.qoff[i])
-        nb = i + 1
+    done = []
+    for s in streams:
+        uf = oracle.UnionFind(s.n)
+        nb = 0
+        for i in range(s.num_batches):
+            uf.bulk_update(s.batch(i))
+            uf.bulk_query(s.query(i))
+            edges += int(s.eoff[i + 1] - s.eoff[i])
+            queries += int(s.qoff[i + 1] - s.qoff[i])
+            nb = i + 1
+            if time.perf_counter() - t0 > budget_s:
+                break
+        done.append((s.name, nb, s.num_batches))
         if time.perf_counter() - t0 > budget_s:
             break
     dt = time.perf_counter() - t0
+    what = "; ".join("%s: %d of %d minibatches" % d for d in done[:3])
+    if len(done) > 3:
+        what += "; ... %d streams in all" % len(done)
     return {"value": (edges + queries) / dt, "unit": "edges+queries/s", "cores": 1, "kind": "oracle",
-            "sample": "first %d of %d minibatches with their query batches (%d edges, %d queries, %.1f s)"
-                      % (nb, s.num_batches, edges, queries, dt),
+            "sample": "%s, each with its query batches (%d edges, %d queries, %.1f s)" % (what, edges, queries, dt),
             "update_edges": edges, "queries": queries, "seconds": dt}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--scale", type=int, default=24, help="R-MAT scale (24 = the headline workload)")
-    ap.add_argument("--options", default="", help="JSON dict of cc_set_option overrides")
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-roofline", action="store_true")
-    args = ap.parse_args()
+def result(value, steps, warmup, wall, config, dtype="int32"):
+    return {"metric": METRIC, "value": value, "unit": "edges+queries/s", "n_gpus": 1, "steps": steps,
+            "warmup": warmup, "ms_per_step": wall / max(1, steps) * 1e3, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
 
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU only; --gpus %d (WORLD_SIZE=%d) is not supported"
-              % (args.gpus, world), file=sys.stderr)
-        sys.exit(2)
 
-    import numpy as np
+# ---------------------------------------------------------------------------
+
+def run_rmat(args):
     import torch
 
     import synth
-    from paper_1602_05232_amd import build as hipbuild
-    if not os.path.exists(hipbuild.OUT):
-        import __graft_entry__
-        __graft_entry__.build()
     import paper_1602_05232_amd as ccgpu
     from paper_1602_05232_amd import roofline, tuning
 
@@ -131,7 +129,6 @@ def main():
     log("generated %s: n=%d edges=%d minibatches=%d queries=%d in %.1fs"
         % (s.name, s.n, len(s.edges), s.num_batches, len(s.queries), time.perf_counter() - t))
     M, Qn, nb = len(s.edges), len(s.queries), s.num_batches
-
     opts = tuning.plain_options(s.n, workload="rmat")
     if args.options:
         opts.update(json.loads(args.options))
@@ -147,7 +144,7 @@ def main():
     stream = torch.cuda.current_stream()
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(nb)]
 
-    def step(k):
+    def step():
         g.reset()
         for i in range(nb):
             ev[i][0].record(stream)
@@ -159,13 +156,13 @@ def main():
         return g.num_components()  # waits for the stream
 
     for k in range(args.warmup):
-        c = step(k)
+        c = step()
         log("warmup step %d done: components=%d" % (k, c))
     torch.cuda.synchronize()
     upd_t, qry_t, upd_lat = [], [], []
     t0 = time.perf_counter()
     for k in range(args.steps):
-        c = step(k)
+        c = step()
         tu = [ev[i][0].elapsed_time(ev[i][1]) / 1e3 for i in range(nb)]
         tq = [ev[i][1].elapsed_time(ev[i][2]) / 1e3 for i in range(nb)]
         upd_t.append(sum(tu))
@@ -180,30 +177,23 @@ def main():
     steps = max(1, args.steps)
     upd_rate = steps * M / sum(upd_t)
     qry_rate = steps * Qn / sum(qry_t)
-
-    res = {
-        "metric": METRIC, "value": steps * (M + Qn) / wall, "unit": "edges+queries/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / steps * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
-        "data": "synthetic",
-        "config": {"workload": "rmat%d-plain" % args.scale, "n": s.n, "edges": M, "minibatches": nb,
-                   "minibatch_sizes": "log-uniform in [2^16, 2^24]", "queries_per_minibatch": qoff[1] - qoff[0],
-                   "rmat_abcd": [0.57, 0.19, 0.19, 0.05], "form": "plain", "options": opts},
-        "update_edges_per_s": upd_rate, "queries_per_s": qry_rate,
-        "update_op_ms": {"p50": pct(upd_lat, 50), "p99": pct(upd_lat, 99)},
-        "components": c, "paper_context": PAPER_CONTEXT,
-    }
+    res = result(steps * (M + Qn) / wall, args.steps, args.warmup, wall, {
+        "workload": "rmat%d-plain" % args.scale, "n": s.n, "edges": M, "minibatches": nb,
+        "minibatch_sizes": "log-uniform in [2^16, 2^24]", "queries_per_minibatch": qoff[1] - qoff[0],
+        "rmat_abcd": [0.57, 0.19, 0.19, 0.05], "form": "plain", "options": opts})
+    res.update({"update_edges_per_s": upd_rate, "queries_per_s": qry_rate,
+                "update_op_ms": {"p50": pct(upd_lat, 50), "p99": pct(upd_lat, 99)},
+                "components": c, "paper_context": PAPER_CONTEXT})
     if not args.no_roofline:
-        tag = "update_fused_rmat%d" % args.scale if opts.get("update_mode", 0) == 0 else \
-            "update_split_rmat%d" % args.scale
+        fused = opts.get("update_mode", 0) == 0
+        tag = ("update_fused_rmat%d" if fused else "update_split_rmat%d") % args.scale
         achieved = UPDATE_BYTES_PER_EDGE * upd_rate / 1e9
         res["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic(tag),
-                           "kernel": "k_update_fused" if opts.get("update_mode", 0) == 0 else
-                           "k_filter+k_link_live+k_compress_live",
+                           "kernel": "k_update_fused" if fused else "k_filter+k_link_live+k_compress_live",
                            "bytes_per_edge": UPDATE_BYTES_PER_EDGE,
-                           "avg_launch_ms": sum(upd_t) / (steps * nb) * 1e3,
-                           "bytes_per_launch": UPDATE_BYTES_PER_EDGE * M / nb}
+                           "avg_update_ms": sum(upd_t) / (steps * nb) * 1e3,
+                           "bytes_per_update": UPDATE_BYTES_PER_EDGE * M / nb}
         del E, Q
         torch.cuda.empty_cache()
         G = roofline.gather_rate(s.n)
@@ -214,13 +204,206 @@ def main():
             "G_gathers_per_s_table_n": G, "G_gathers_per_s_table_2^30": Gbig, "stream_read_GBs": Bs / 1e9,
             "E_roof_edges_per_s": Eroof, "frac": upd_rate / Eroof,
             "E_roof_beyond_cache_edges_per_s": roofline.edge_roofline(Gbig, Bs),
+            "query_roof_per_s": G / 2.0, "query_frac": qry_rate / (G / 2.0),
             "note": "E_roof = 1/(2/G + 8/B_s): two random parent reads and 8 streamed bytes per edge"}
         log("gather roofline: G(n)=%.3g/s G(2^30)=%.3g/s B_s=%.1f GB/s E_roof=%.3g e/s frac=%.3f"
             % (G, Gbig, Bs / 1e9, Eroof, upd_rate / Eroof))
     g.close()
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(s, args.cpu_budget)
+        res["cpu_baseline"] = cpu_baseline([s], args.cpu_budget)
         log("cpu baseline: %s" % res["cpu_baseline"]["sample"])
+    return res
+
+
+def run_grid(args):
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_1602_05232_amd as ccgpu
+    from paper_1602_05232_amd import tuning
+
+    t = time.perf_counter()
+    s = synth.grid_stream_cfg()
+    log("generated %s: n=%d edges=%d minibatches=%d in %.1fs" % (s.name, s.n, len(s.edges), s.num_batches,
+                                                                  time.perf_counter() - t))
+    M, Qn, nb = len(s.edges), len(s.queries), s.num_batches
+    opts = tuning.plain_options(s.n, workload="grid")
+    if args.options:
+        opts.update(json.loads(args.options))
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        E = torch.from_numpy(s.edges).cuda()
+        Q = torch.from_numpy(s.queries).cuda()
+        out = torch.empty(Qn, dtype=torch.uint8, device="cuda")
+        lab = torch.empty(s.n, dtype=torch.int32, device="cuda")
+        g = ccgpu.Graph(s.n, stream=st, **opts)
+        g.reserve(int(np.diff(s.eoff).max()))
+        eoff = [int(x) for x in s.eoff]
+        qoff = [int(x) for x in s.qoff]
+
+        def sequence():
+            g.reset()
+            for i in range(nb):
+                g.bulk_update(E[eoff[i]:eoff[i + 1]])
+                g.bulk_query(Q[qoff[i]:qoff[i + 1]], out=out[qoff[i]:qoff[i + 1]])
+            g.labels(out=lab)
+
+        def timed(fn, steps, warmup, name):
+            for _ in range(warmup):
+                fn()
+                c = g.num_components()
+            st.synchronize()
+            t0 = time.perf_counter()
+            for k in range(steps):
+                fn()
+                c = g.num_components()
+                log("%s step %d done: components=%d" % (name, k, c))
+            st.synchronize()
+            return time.perf_counter() - t0, c
+
+        wall_plain, c1 = timed(sequence, args.steps, args.warmup, "plain")
+        want = out.clone()
+        t = time.perf_counter()
+        with g.capture() as cap:
+            sequence()
+        rec = cap.recording
+        log("captured %d minibatches in %.2fs" % (nb, time.perf_counter() - t))
+        wall_graph, c2 = timed(rec.launch, args.steps, args.warmup, "graph")
+        assert c1 == c2 and torch.equal(out, want), "replay differs from plain launches"
+        assert g.sync() == 0
+        rec.close()
+        g.close()
+    steps = max(1, args.steps)
+    res = result(steps * (M + Qn) / wall_graph, args.steps, args.warmup, wall_graph, {
+        "workload": "grid4096-graph", "n": s.n, "edges": M, "minibatches": nb, "minibatch": 1 << 12,
+        "queries_per_minibatch": 1 << 10, "long_range_edges": s.meta["extra"], "form": "hipgraph",
+        "options": opts})
+    res.update({"plain_value": steps * (M + Qn) / wall_plain, "plain_ms_per_step": wall_plain / steps * 1e3,
+                "speedup_vs_plain": wall_plain / wall_graph, "components": c2})
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline([s], args.cpu_budget)
+    return res
+
+
+def run_batched(args):
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_1602_05232_amd as ccgpu
+    from paper_1602_05232_amd import tuning
+
+    t = time.perf_counter()
+    ns = synth.multi_graph_sizes(G=args.graphs)
+    streams = [synth.multi_graph_stream(g, int(ns[g])) for g in range(args.graphs)]
+    M = sum(len(s.edges) for s in streams)
+    Qn = sum(len(s.queries) for s in streams)
+    log("generated %d graphs: sum n=%d edges=%d queries=%d in %.1fs"
+        % (len(streams), int(ns.sum()), M, Qn, time.perf_counter() - t))
+    # all inputs in two device buffers
+    Eall = torch.from_numpy(np.concatenate([s.edges for s in streams])).cuda()
+    Qall = torch.from_numpy(np.concatenate([s.queries for s in streams])).cuda()
+    out = torch.empty(Qn, dtype=torch.uint8, device="cuda")
+    ebase = np.cumsum([0] + [len(s.edges) for s in streams])
+    qbase = np.cumsum([0] + [len(s.queries) for s in streams])
+    G = len(streams)
+
+    def eslice(g, k):
+        s = streams[g]
+        return Eall[int(ebase[g] + s.eoff[k]):int(ebase[g] + s.eoff[k + 1])]
+
+    def qslice(g, k, buf):
+        s = streams[g]
+        return buf[int(qbase[g] + s.qoff[k]):int(qbase[g] + s.qoff[k + 1])]
+
+    popts = tuning.lookup("pool", "mixed", int(np.median(ns))) or {}
+    popts = {k: v for k, v in popts.items() if k not in ("update_mode", "compress_every")}
+    if args.options:
+        popts.update(json.loads(args.options))
+    pool = ccgpu.Pool(int(ns.sum()), G, **popts)
+    ids = [pool.add(s.n) for s in streams]
+    ops_per_step = []
+    for k in range(4):
+        ops = [(ids[g], ccgpu.UPDATE, eslice(g, k), None) for g in range(G)]
+        ops += [(ids[g], ccgpu.QUERY, qslice(g, k, Qall), qslice(g, k, out)) for g in range(G)]
+        ops_per_step.append(ops)
+
+    def pool_step():
+        pool.reset_all()
+        for ops in ops_per_step:
+            pool.run(ops)
+        return pool.sync()
+
+    graphs = [ccgpu.Graph(s.n) for s in streams]
+    out_plain = torch.empty_like(out)
+
+    def plain_step():
+        for gr in graphs:
+            gr.reset()
+        for k in range(4):
+            for g in range(G):
+                graphs[g].bulk_update(eslice(g, k))
+            for g in range(G):
+                graphs[g].bulk_query(qslice(g, k, Qall), out=qslice(g, k, out_plain))
+        torch.cuda.synchronize()
+
+    def timed(fn, name):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            fn()
+            log("%s step %d done" % (name, k))
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    wall_plain = timed(plain_step, "per-graph")
+    wall_pool = timed(pool_step, "pool")
+    assert torch.equal(out, out_plain), "pool answers differ from per-graph answers"
+    comps = sum(pool.num_components(i) for i in ids)
+    assert comps == sum(gr.num_components() for gr in graphs)
+    for gr in graphs:
+        gr.close()
+    pool.close()
+    steps = max(1, args.steps)
+    res = result(steps * (M + Qn) / wall_pool, args.steps, args.warmup, wall_pool, {
+        "workload": "batched%d-pool" % G, "graphs": G, "sum_n": int(ns.sum()), "median_n": int(np.median(ns)),
+        "edges": M, "queries": Qn, "steps_per_graph": 4, "queries_per_step": 1 << 12,
+        "n_distribution": "clip(round(2^X), 2^10, 2^20), X ~ N(14, 2)", "form": "pool", "options": popts})
+    res.update({"plain_value": steps * (M + Qn) / wall_plain, "plain_ms_per_step": wall_plain / steps * 1e3,
+                "speedup_vs_plain": wall_plain / wall_pool, "components": comps})
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(streams, args.cpu_budget)
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="rmat24", choices=["rmat24", "grid4096", "batched1024"])
+    ap.add_argument("--scale", type=int, default=24, help="R-MAT scale of the rmat24 workload")
+    ap.add_argument("--graphs", type=int, default=1024, help="graphs of the batched workload")
+    ap.add_argument("--options", default="", help="JSON dict of option overrides")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-roofline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on one GPU only; --gpus %d (WORLD_SIZE=%d) is not supported"
+              % (args.gpus, world), file=sys.stderr)
+        sys.exit(2)
+
+    from paper_1602_05232_amd import build as hipbuild
+    if not os.path.exists(hipbuild.OUT):
+        import __graft_entry__
+        __graft_entry__.build()
+    res = {"rmat24": run_rmat, "grid4096": run_grid, "batched1024": run_batched}[args.workload](args)
     print(json.dumps(res), flush=True)
 
 

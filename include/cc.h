@@ -152,6 +152,24 @@ int64_t cc_state_bytes(const cc_graph* g);
 int cc_save(cc_graph* g, void* host_buf);
 int cc_load(cc_graph* g, const void* host_buf);
 
+/* Capture and replay with a HIP graph, for streams of many small minibatches
+ * whose cost is dominated by launch overhead.  Between cc_capture_begin(g)
+ * and cc_capture_end(g, &x) the calls cc_reset, cc_bulk_update, cc_bulk_query
+ * and cc_labels on g are recorded instead of run; cc_exec_launch(x) then runs
+ * the whole recorded sequence, in order, with one launch on g's stream,
+ * reading and writing the same caller buffers each time (their contents may
+ * change between launches).  g's stream must not be the null stream.  During
+ * capture, calls that wait for the device (cc_num_components, cc_count_roots,
+ * cc_sync, cc_save, cc_load, cc_reserve, cc_destroy) return CC_EINVAL, and so
+ * does a split-schedule update larger than the size reserved before the
+ * capture.  The recorded work uses no memset nodes.  Ownership: the caller
+ * releases x with cc_exec_destroy, before destroying g. */
+typedef struct cc_exec cc_exec;
+int cc_capture_begin(cc_graph* g);
+int cc_capture_end(cc_graph* g, cc_exec** out);
+int cc_exec_launch(cc_exec* x);
+int cc_exec_destroy(cc_exec* x);
+
 /* Vertex count of g (0 for NULL). */
 int64_t cc_num_vertices(const cc_graph* g);
 

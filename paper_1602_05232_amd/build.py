@@ -10,7 +10,7 @@ OUT = os.path.join(HERE, "libcc.so")
 ARCH = "gfx950"
 
 # Translation units linked into libcc.so.
-SOURCES = ["cc_plain.hip", "cc_bench.hip"]
+SOURCES = ["cc_plain.hip", "cc_pool.hip", "cc_bench.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",

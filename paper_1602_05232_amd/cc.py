@@ -42,9 +42,44 @@ SIGNATURES = {
     "cc_save": (_i32, [_vp, _vp]),
     "cc_load": (_i32, [_vp, _vp]),
     "cc_num_vertices": (_i64, [_vp]),
+    "cc_capture_begin": (_i32, [_vp]),
+    "cc_capture_end": (_i32, [_vp, ctypes.POINTER(_vp)]),
+    "cc_exec_launch": (_i32, [_vp]),
+    "cc_exec_destroy": (_i32, [_vp]),
     "cc_strerror": (ctypes.c_char_p, [_i32]),
     "cc_last_error": (ctypes.c_char_p, []),
 }
+
+# include/cc_pool.h (many graphs in one arena)
+POOL_SIGNATURES = {
+    "cc_pool_create": (_vp, [_i64, _i32]),
+    "cc_pool_destroy": (_i32, [_vp]),
+    "cc_pool_set_stream": (_i32, [_vp, _vp]),
+    "cc_pool_set_option": (_i32, [_vp, _i32, _i64]),
+    "cc_pool_add": (_i32, [_vp, _i64, ctypes.POINTER(ctypes.c_int32)]),
+    "cc_pool_remove": (_i32, [_vp, _i32]),
+    "cc_pool_reset": (_i32, [_vp, _i32]),
+    "cc_pool_reset_all": (_i32, [_vp]),
+    "cc_pool_graph_vertices": (_i64, [_vp, _i32]),
+    "cc_pool_free_vertices": (_i64, [_vp]),
+    "cc_pool_largest_gap": (_i64, [_vp]),
+    "cc_pool_run": (_i32, [_vp, _vp, _i32]),
+    "cc_pool_labels": (_i32, [_vp, _i32, _vp]),
+    "cc_pool_num_components": (_i32, [_vp, _i32, ctypes.POINTER(_i64)]),
+    "cc_pool_sync": (_i32, [_vp]),
+    "cc_pool_state_bytes": (_i64, [_vp, _i32]),
+    "cc_pool_save": (_i32, [_vp, _i32, _vp]),
+    "cc_pool_load": (_i32, [_vp, _i32, _vp]),
+}
+
+
+class CcOp(ctypes.Structure):
+    """struct cc_op of include/cc_pool.h."""
+    _fields_ = [("graph", ctypes.c_int32), ("kind", ctypes.c_int32), ("count", ctypes.c_int64),
+                ("items", ctypes.c_void_p), ("out", ctypes.c_void_p)]
+
+
+UPDATE, QUERY = 0, 1
 
 # include/cc_bench.h (memory-system microbenchmarks for roofline denominators)
 BENCH_SIGNATURES = {
@@ -67,7 +102,7 @@ def _name(code):
 
 
 def load_library(path: str = LIB_PATH, declare=None):
-    declare = declare if declare is not None else {**SIGNATURES, **BENCH_SIGNATURES}
+    declare = declare if declare is not None else {**SIGNATURES, **POOL_SIGNATURES, **BENCH_SIGNATURES}
     if not os.path.exists(path):
         raise ImportError("%s is not built; run __graft_entry__.build() first" % path)
     L = ctypes.CDLL(path)
@@ -196,6 +231,11 @@ class Graph:
             return rc
         return _check(rc)
 
+    def capture(self):
+        """Context manager: calls on this graph inside the block are recorded
+        into a replayable sequence (the returned Recording after exit)."""
+        return _Capture(self)
+
     def save(self) -> bytearray:
         buf = bytearray(int(lib().cc_state_bytes(self._h)))
         cbuf = (ctypes.c_char * len(buf)).from_buffer(buf)
@@ -208,3 +248,153 @@ class Graph:
         if len(buf) != lib().cc_state_bytes(self._h):
             raise CCError(CC_EINVAL, "state image has the wrong size")
         _check(lib().cc_load(self._h, ctypes.addressof(cbuf)))
+
+
+class Recording:
+    """A captured sequence of calls on one graph (cc_exec)."""
+
+    def __init__(self, h):
+        self._h = h
+
+    def launch(self):
+        _check(lib().cc_exec_launch(self._h))
+
+    def close(self):
+        if self._h:
+            lib().cc_exec_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class _Capture:
+    def __init__(self, g: Graph):
+        self.g = g
+        self.recording = None
+
+    def __enter__(self):
+        _check(lib().cc_capture_begin(self.g.handle))
+        return self
+
+    def __exit__(self, et, ev, tb):
+        x = ctypes.c_void_p()
+        rc = lib().cc_capture_end(self.g.handle, ctypes.byref(x))
+        if et is None:
+            _check(rc)
+            self.recording = Recording(x.value)
+        elif rc == CC_OK:
+            lib().cc_exec_destroy(x.value)
+        return False
+
+
+class Pool:
+    """Many independent graphs in one device arena (include/cc_pool.h).
+
+    run() takes a list of (graph, kind, items, out) with kind UPDATE (items =
+    int32 [k, 2] edges, out None) or QUERY (items = pairs, out = uint8 [k]);
+    operations on one graph apply in list order, one launch per round."""
+
+    def __init__(self, capacity: int, max_graphs: int, stream=None, **options):
+        self._h = None
+        L = lib()
+        h = L.cc_pool_create(int(capacity), int(max_graphs))
+        if not h:
+            raise CCError(CC_ENOMEM, L.cc_last_error().decode(errors="replace"))
+        self._h = h
+        self.capacity = int(capacity)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        _check(L.cc_pool_set_stream(h, stream_handle(self.stream)))
+        for k, v in options.items():
+            self.set_option(k, v)
+
+    def close(self):
+        if self._h:
+            lib().cc_pool_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream):
+        self.stream = stream
+        _check(lib().cc_pool_set_stream(self._h, stream_handle(stream)))
+
+    def set_option(self, key, value: int):
+        k = _OPT_NAMES[key] if isinstance(key, str) else int(key)
+        _check(lib().cc_pool_set_option(self._h, k, int(value)))
+
+    def add(self, n: int) -> int:
+        gid = ctypes.c_int32()
+        _check(lib().cc_pool_add(self._h, int(n), ctypes.byref(gid)))
+        return gid.value
+
+    def remove(self, gid: int):
+        _check(lib().cc_pool_remove(self._h, int(gid)))
+
+    def reset(self, gid: int):
+        _check(lib().cc_pool_reset(self._h, int(gid)))
+
+    def reset_all(self):
+        _check(lib().cc_pool_reset_all(self._h))
+
+    def vertices(self, gid: int) -> int:
+        return int(lib().cc_pool_graph_vertices(self._h, int(gid)))
+
+    def free_vertices(self) -> int:
+        return int(lib().cc_pool_free_vertices(self._h))
+
+    def largest_gap(self) -> int:
+        return int(lib().cc_pool_largest_gap(self._h))
+
+    def run(self, ops):
+        arr = (CcOp * max(1, len(ops)))()
+        for i, (gid, kind, items, out) in enumerate(ops):
+            cnt = items.shape[0] if items is not None and items.numel() else 0
+            arr[i].graph = int(gid)
+            arr[i].kind = int(kind)
+            arr[i].count = cnt
+            arr[i].items = _pairs_ptr(items, "items") if cnt else None
+            if kind == QUERY and cnt:
+                assert out is not None and out.dtype == torch.uint8 and out.is_cuda and out.numel() >= cnt
+                arr[i].out = out.data_ptr()
+            else:
+                arr[i].out = None
+        _check(lib().cc_pool_run(self._h, arr, len(ops)))
+
+    def labels(self, gid: int, out: torch.Tensor | None = None) -> torch.Tensor:
+        n = self.vertices(gid)
+        if out is None:
+            out = torch.empty(n, dtype=torch.int32, device="cuda")
+        _check(lib().cc_pool_labels(self._h, int(gid), out.data_ptr()))
+        return out
+
+    def num_components(self, gid: int) -> int:
+        v = ctypes.c_int64()
+        _check(lib().cc_pool_num_components(self._h, int(gid), ctypes.byref(v)))
+        return v.value
+
+    def sync(self) -> int:
+        rc = lib().cc_pool_sync(self._h)
+        if rc in (CC_OK, CC_ERANGE, CC_ECORRUPT):
+            return rc
+        return _check(rc)
+
+    def save(self, gid: int) -> bytearray:
+        buf = bytearray(int(lib().cc_pool_state_bytes(self._h, int(gid))))
+        cbuf = (ctypes.c_char * len(buf)).from_buffer(buf)
+        _check(lib().cc_pool_save(self._h, int(gid), ctypes.addressof(cbuf)))
+        return buf
+
+    def load(self, gid: int, buf):
+        buf = bytearray(buf)
+        if len(buf) != lib().cc_pool_state_bytes(self._h, int(gid)):
+            raise CCError(CC_EINVAL, "state image has the wrong size")
+        cbuf = (ctypes.c_char * len(buf)).from_buffer(buf)
+        _check(lib().cc_pool_load(self._h, int(gid), ctypes.addressof(cbuf)))

@@ -1,6 +1,7 @@
 // Host-side helpers shared by the library's translation units.
 #pragma once
 
+#include <hip/hip_runtime.h>
 #include <stdarg.h>
 #include <stdint.h>
 
@@ -8,7 +9,36 @@
 
 void cc_set_error(const char* fmt, ...);
 
+#define HIP_TRY(expr)                                                               \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess) {                                                         \
+      cc_set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                   __LINE__);                                                       \
+      return CC_EDEVICE;                                                            \
+    }                                                                               \
+  } while (0)
+
 namespace cc {
+
+// Makes `dev` current for the lifetime of the guard.
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+    else prev = -1;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+inline unsigned blocks_for(int64_t items, int64_t per_block, int cap) {
+  int64_t b = (items + per_block - 1) / per_block;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return (unsigned)b;
+}
 
 struct Tuning {
   int mode = 0;             // CC_OPT_UPDATE_MODE

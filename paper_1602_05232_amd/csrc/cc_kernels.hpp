@@ -21,6 +21,7 @@
 #include "uf_device.hpp"
 
 namespace ccdev {
+namespace {  // kernels get internal linkage in every translation unit
 
 __global__ void k_init(int32_t* __restrict__ parent, int64_t n) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -106,7 +107,7 @@ __global__ void k_update_fused(int32_t* __restrict__ parent, const int2* __restr
       const int32_t ru = find_halve_from(parent, u, pu, n, flags);
       const int32_t rv = find_halve_from(parent, v, pv, n, flags);
       if (ru != rv) {
-        hk[k] = link_roots<Ord>(parent, ru, rv, n, flags);
+        hk[k] = link_roots(parent, ru, rv, n, flags, Ord{});
         if (hk[k] >= 0) ++nh;
       }
     }
@@ -187,7 +188,7 @@ __global__ void k_link_live(int32_t* __restrict__ parent, const int2* __restrict
   int links = 0;
   for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < L; i += gridDim.x * blockDim.x) {
     const int2 p = live[i];
-    links += link_roots<Ord>(parent, p.x, p.y, n, flags) >= 0;
+    links += link_roots(parent, p.x, p.y, n, flags, Ord{}) >= 0;
   }
   count_links(slots, links);
 }
@@ -334,4 +335,5 @@ __global__ void k_count_roots(const int32_t* __restrict__ parent, int32_t n,
   }
 }
 
+}  // namespace
 }  // namespace ccdev

@@ -14,6 +14,8 @@
 #include "cc_internal.hpp"
 
 using namespace ccdev;
+using cc::blocks_for;
+using cc::DeviceGuard;
 
 namespace {
 thread_local char g_err[512] = "";
@@ -40,16 +42,6 @@ extern "C" const char* cc_strerror(int code) {
   }
 }
 
-#define HIP_TRY(expr)                                                               \
-  do {                                                                              \
-    hipError_t e_ = (expr);                                                         \
-    if (e_ != hipSuccess) {                                                         \
-      cc_set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
-                   __LINE__);                                                       \
-      return CC_EDEVICE;                                                            \
-    }                                                                               \
-  } while (0)
-
 struct cc_graph {
   int64_t n = 0;
   int device = 0;
@@ -63,21 +55,17 @@ struct cc_graph {
   int32_t* hooked = nullptr;     // roots linked by the last fused update (n entries)
   int64_t live_cap = 0;
   int64_t updates = 0;
+  bool capturing = false;
   cc::Tuning tune;
 };
 
-namespace {
-
-struct DeviceGuard {
-  int prev = -1;
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
-    else prev = -1;
-  }
-  ~DeviceGuard() {
-    if (prev >= 0) hipSetDevice(prev);
-  }
+struct cc_exec {
+  hipGraphExec_t exec = nullptr;
+  hipStream_t stream = nullptr;
+  int device = 0;
 };
+
+namespace {
 
 int alloc_live(cc_graph* g, int64_t cap) {
   if (cap <= g->live_cap) return CC_OK;
@@ -104,13 +92,6 @@ int alloc_hooked(cc_graph* g) {
     return CC_ENOMEM;
   }
   return CC_OK;
-}
-
-inline unsigned blocks_for(int64_t items, int64_t per_block, int cap) {
-  int64_t b = (items + per_block - 1) / per_block;
-  if (b < 1) b = 1;
-  if (b > cap) b = cap;
-  return (unsigned)b;
 }
 
 int launch_init(cc_graph* g) {
@@ -247,6 +228,10 @@ extern "C" cc_graph* cc_create(int64_t n) {
 
 extern "C" int cc_destroy(cc_graph* g) {
   if (!g) return CC_EINVAL;
+  if (g->capturing) {
+    cc_set_error("call not allowed while capturing");
+    return CC_EINVAL;
+  }
   DeviceGuard dg(g->device);
   (void)hipStreamSynchronize(g->stream);
   (void)hipFree(g->parent);
@@ -282,6 +267,10 @@ extern "C" int cc_get_option(cc_graph* g, int key, int64_t* value) {
 
 extern "C" int cc_reserve(cc_graph* g, int64_t max_batch) {
   if (!g || max_batch < 0) return CC_EINVAL;
+  if (g->capturing) {
+    cc_set_error("call not allowed while capturing");
+    return CC_EINVAL;
+  }
   DeviceGuard dg(g->device);
   int rc = alloc_hooked(g);
   if (rc != CC_OK) return rc;
@@ -305,12 +294,21 @@ extern "C" int cc_bulk_update(cc_graph* g, const int32_t* edges, int64_t m) {
   const int2* e = reinterpret_cast<const int2*>(edges);
   const bool hashed = g->tune.hook == 1;
   if (g->tune.mode == 1) {
+    if (g->capturing && m > g->live_cap) {
+      cc_set_error("cc_bulk_update: split update of %lld edges exceeds the reserved %lld during capture",
+                   (long long)m, (long long)g->live_cap);
+      return CC_EINVAL;
+    }
     int rc = alloc_live(g, m);
     if (rc != CC_OK) return rc;
     if (hashed) launch_split_o<ByHash>(g, e, m);
     else launch_split_o<ById>(g, e, m);
   } else {
-    if (g->tune.compress_linked) {
+    if (g->tune.compress_linked && !g->hooked) {
+      if (g->capturing) {
+        cc_set_error("cc_bulk_update: call cc_reserve before capturing");
+        return CC_EINVAL;
+      }
       int rc = alloc_hooked(g);
       if (rc != CC_OK) return rc;
     }
@@ -357,6 +355,10 @@ extern "C" int cc_labels(cc_graph* g, int32_t* out) {
 
 extern "C" int cc_num_components(cc_graph* g, int64_t* out) {
   if (!g || !out) return CC_EINVAL;
+  if (g->capturing) {
+    cc_set_error("call not allowed while capturing");
+    return CC_EINVAL;
+  }
   DeviceGuard dg(g->device);
   unsigned long long links = 0;
   int rc = read_links(g, &links);
@@ -367,6 +369,10 @@ extern "C" int cc_num_components(cc_graph* g, int64_t* out) {
 
 extern "C" int cc_count_roots(cc_graph* g, int64_t* out) {
   if (!g || !out) return CC_EINVAL;
+  if (g->capturing) {
+    cc_set_error("call not allowed while capturing");
+    return CC_EINVAL;
+  }
   DeviceGuard dg(g->device);
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, g->stream, g->red, 1);
   hipLaunchKernelGGL(k_count_roots, dim3(vertex_blocks(g)), dim3(256), 0, g->stream, g->parent,
@@ -381,6 +387,10 @@ extern "C" int cc_count_roots(cc_graph* g, int64_t* out) {
 
 extern "C" int cc_sync(cc_graph* g) {
   if (!g) return CC_EINVAL;
+  if (g->capturing) {
+    cc_set_error("call not allowed while capturing");
+    return CC_EINVAL;
+  }
   DeviceGuard dg(g->device);
   HIP_TRY(hipStreamSynchronize(g->stream));
   int f = 0;
@@ -407,6 +417,10 @@ extern "C" int64_t cc_state_bytes(const cc_graph* g) { return g ? 16 + 4 * g->n 
 
 extern "C" int cc_save(cc_graph* g, void* host_buf) {
   if (!g || !host_buf) return CC_EINVAL;
+  if (g->capturing) {
+    cc_set_error("call not allowed while capturing");
+    return CC_EINVAL;
+  }
   DeviceGuard dg(g->device);
   unsigned long long links = 0;
   int rc = read_links(g, &links);
@@ -420,6 +434,10 @@ extern "C" int cc_save(cc_graph* g, void* host_buf) {
 
 extern "C" int cc_load(cc_graph* g, const void* host_buf) {
   if (!g || !host_buf) return CC_EINVAL;
+  if (g->capturing) {
+    cc_set_error("call not allowed while capturing");
+    return CC_EINVAL;
+  }
   DeviceGuard dg(g->device);
   int64_t hdr[2];
   memcpy(hdr, host_buf, 16);
@@ -439,5 +457,58 @@ extern "C" int cc_load(cc_graph* g, const void* host_buf) {
   HIP_TRY(hipMemcpyAsync(g->parent, p, (size_t)g->n * 4, hipMemcpyHostToDevice, g->stream));
   HIP_TRY(hipMemcpyAsync(g->slots, h.data(), h.size() * 8, hipMemcpyHostToDevice, g->stream));
   HIP_TRY(hipStreamSynchronize(g->stream));
+  return CC_OK;
+}
+
+extern "C" int cc_capture_begin(cc_graph* g) {
+  if (!g || g->capturing || !g->stream) {
+    cc_set_error("cc_capture_begin: needs a graph on a non-null stream, not already capturing");
+    return CC_EINVAL;
+  }
+  DeviceGuard dg(g->device);
+  int rc = alloc_hooked(g);  // allocations cannot happen inside the capture
+  if (rc != CC_OK) return rc;
+  HIP_TRY(hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal));
+  g->capturing = true;
+  return CC_OK;
+}
+
+extern "C" int cc_capture_end(cc_graph* g, cc_exec** out) {
+  if (!g || !out || !g->capturing) return CC_EINVAL;
+  DeviceGuard dg(g->device);
+  g->capturing = false;
+  hipGraph_t graph = nullptr;
+  HIP_TRY(hipStreamEndCapture(g->stream, &graph));
+  cc_exec* x = new (std::nothrow) cc_exec();
+  if (!x) {
+    (void)hipGraphDestroy(graph);
+    return CC_ENOMEM;
+  }
+  hipError_t e = hipGraphInstantiate(&x->exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    cc_set_error("hipGraphInstantiate: %s", hipGetErrorString(e));
+    delete x;
+    return CC_EDEVICE;
+  }
+  x->stream = g->stream;
+  x->device = g->device;
+  *out = x;
+  return CC_OK;
+}
+
+extern "C" int cc_exec_launch(cc_exec* x) {
+  if (!x) return CC_EINVAL;
+  DeviceGuard dg(x->device);
+  HIP_TRY(hipGraphLaunch(x->exec, x->stream));
+  return CC_OK;
+}
+
+extern "C" int cc_exec_destroy(cc_exec* x) {
+  if (!x) return CC_EINVAL;
+  DeviceGuard dg(x->device);
+  (void)hipStreamSynchronize(x->stream);
+  (void)hipGraphExecDestroy(x->exec);
+  delete x;
   return CC_OK;
 }

@@ -1,0 +1,499 @@
+// C ABI of the many-graph pool (include/cc_pool.h).
+#include <hip/hip_runtime.h>
+
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "../../include/cc_pool.h"
+#include "cc_internal.hpp"
+#include "cc_pool_kernels.hpp"
+
+using namespace ccdev;
+using cc::blocks_for;
+using cc::DeviceGuard;
+
+namespace {
+
+constexpr int kRing = 4;  // descriptor staging slots in flight
+
+struct PoolGraph {
+  int64_t base = 0, n = 0;
+  bool used = false;
+};
+
+struct RingSlot {
+  OpDesc* host = nullptr;  // pinned staging
+  OpDesc* dev = nullptr;
+  int64_t cap = 0;
+  hipEvent_t done = nullptr;
+  bool pending = false;
+};
+
+}  // namespace
+
+struct cc_pool {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int64_t capacity = 0;
+  int32_t max_graphs = 0;
+  int32_t* arena = nullptr;
+  unsigned long long* glinks = nullptr;  // max_graphs * kPoolLinkStride
+  int* flags = nullptr;
+  int32_t* hooked = nullptr;  // capacity entries
+  unsigned* ctl = nullptr;    // [0] hooked count, [1] finished blocks
+  std::vector<PoolGraph> graphs;
+  std::map<int64_t, int64_t> gaps;  // base -> length of each free range
+  RingSlot ring[kRing];
+  int ring_next = 0;
+  cc::Tuning tune;
+};
+
+namespace {
+
+bool valid_graph(const cc_pool* p, int32_t id) {
+  return p && id >= 0 && id < p->max_graphs && p->graphs[(size_t)id].used;
+}
+
+int64_t take_gap(cc_pool* p, int64_t n) {
+  for (auto it = p->gaps.begin(); it != p->gaps.end(); ++it) {
+    if (it->second >= n) {
+      const int64_t base = it->first, len = it->second;
+      p->gaps.erase(it);
+      if (len > n) p->gaps[base + n] = len - n;
+      return base;
+    }
+  }
+  return -1;
+}
+
+void give_gap(cc_pool* p, int64_t base, int64_t n) {
+  auto it = p->gaps.emplace(base, n).first;
+  auto nx = std::next(it);
+  if (nx != p->gaps.end() && it->first + it->second == nx->first) {
+    it->second += nx->second;
+    p->gaps.erase(nx);
+  }
+  if (it != p->gaps.begin()) {
+    auto pv = std::prev(it);
+    if (pv->first + pv->second == it->first) {
+      pv->second += it->second;
+      p->gaps.erase(it);
+    }
+  }
+}
+
+int reserve_slot(cc_pool* p, int64_t count, RingSlot** out) {
+  RingSlot* s = &p->ring[p->ring_next];
+  p->ring_next = (p->ring_next + 1) % kRing;
+  if (s->pending) {
+    HIP_TRY(hipEventSynchronize(s->done));
+    s->pending = false;
+  }
+  if (s->cap < count) {
+    if (s->host) (void)hipHostFree(s->host);
+    if (s->dev) (void)hipFree(s->dev);
+    s->host = nullptr;
+    s->dev = nullptr;
+    s->cap = 0;
+    const int64_t cap = std::max<int64_t>(count, 1024);
+    if (hipHostMalloc((void**)&s->host, (size_t)cap * sizeof(OpDesc), hipHostMallocDefault) != hipSuccess ||
+        hipMalloc((void**)&s->dev, (size_t)cap * sizeof(OpDesc)) != hipSuccess) {
+      cc_set_error("cc_pool_run: descriptor staging allocation failed");
+      return CC_ENOMEM;
+    }
+    s->cap = cap;
+  }
+  *out = s;
+  return CC_OK;
+}
+
+template <int ITEMS, bool HASH, bool RECORD>
+void launch_phase_t(cc_pool* p, const OpDesc* d, int nops, uint32_t ntiles) {
+  const int B = p->tune.block;
+  const unsigned grid = (unsigned)std::min<int64_t>(ntiles, p->tune.grid_cap);
+  if (p->tune.query_halving)
+    hipLaunchKernelGGL((k_pool_phase<ITEMS, HASH, RECORD, true>), dim3(grid), dim3(B), 0, p->stream, d, nops,
+                       ntiles, p->arena, p->glinks, p->flags, p->hooked, p->ctl);
+  else
+    hipLaunchKernelGGL((k_pool_phase<ITEMS, HASH, RECORD, false>), dim3(grid), dim3(B), 0, p->stream, d, nops,
+                       ntiles, p->arena, p->glinks, p->flags, p->hooked, p->ctl);
+}
+
+template <int ITEMS>
+void launch_phase_i(cc_pool* p, const OpDesc* d, int nops, uint32_t ntiles, bool record) {
+  const bool hash = p->tune.hook == 1;
+  if (hash) {
+    if (record) launch_phase_t<ITEMS, true, true>(p, d, nops, ntiles);
+    else launch_phase_t<ITEMS, true, false>(p, d, nops, ntiles);
+  } else {
+    if (record) launch_phase_t<ITEMS, false, true>(p, d, nops, ntiles);
+    else launch_phase_t<ITEMS, false, false>(p, d, nops, ntiles);
+  }
+}
+
+void launch_phase(cc_pool* p, int items, const OpDesc* d, int nops, uint32_t ntiles, bool record) {
+  switch (items) {
+    case 1: launch_phase_i<1>(p, d, nops, ntiles, record); break;
+    case 2: launch_phase_i<2>(p, d, nops, ntiles, record); break;
+    case 8: launch_phase_i<8>(p, d, nops, ntiles, record); break;
+    default: launch_phase_i<4>(p, d, nops, ntiles, record); break;
+  }
+}
+
+}  // namespace
+
+extern "C" cc_pool* cc_pool_create(int64_t capacity, int32_t max_graphs) {
+  if (capacity < 1 || capacity > 0x7fffffffLL || max_graphs < 1 || max_graphs > (1 << 24)) {
+    cc_set_error("cc_pool_create: capacity %lld / max_graphs %d out of range", (long long)capacity, max_graphs);
+    return nullptr;
+  }
+  cc_pool* p = new (std::nothrow) cc_pool();
+  if (!p) return nullptr;
+  p->capacity = capacity;
+  p->max_graphs = max_graphs;
+  p->graphs.resize((size_t)max_graphs);
+  p->gaps[0] = capacity;
+  auto fail = [&](const char* what) -> cc_pool* {
+    cc_set_error("cc_pool_create: %s failed", what);
+    (void)hipFree(p->arena);
+    (void)hipFree(p->glinks);
+    (void)hipFree(p->flags);
+    (void)hipFree(p->hooked);
+    (void)hipFree(p->ctl);
+    delete p;
+    return nullptr;
+  };
+  if (hipGetDevice(&p->device) != hipSuccess) return fail("hipGetDevice");
+  if (hipMalloc(&p->arena, (size_t)capacity * 4) != hipSuccess) return fail("arena");
+  if (hipMalloc(&p->glinks, (size_t)max_graphs * kPoolLinkStride * 8) != hipSuccess) return fail("links");
+  if (hipMalloc(&p->flags, 64) != hipSuccess) return fail("flags");
+  if (hipMalloc(&p->hooked, (size_t)capacity * 4) != hipSuccess) return fail("hooked");
+  if (hipMalloc(&p->ctl, 64) != hipSuccess) return fail("ctl");
+  if (hipMemsetAsync(p->flags, 0, 64, p->stream) != hipSuccess) return fail("memset");
+  if (hipMemsetAsync(p->ctl, 0, 64, p->stream) != hipSuccess) return fail("memset");
+  if (hipMemsetAsync(p->glinks, 0, (size_t)max_graphs * kPoolLinkStride * 8, p->stream) != hipSuccess)
+    return fail("memset");
+  for (auto& s : p->ring)
+    if (hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess) return fail("event");
+  if (hipStreamSynchronize(p->stream) != hipSuccess) return fail("sync");
+  return p;
+}
+
+extern "C" int cc_pool_destroy(cc_pool* p) {
+  if (!p) return CC_EINVAL;
+  DeviceGuard dg(p->device);
+  (void)hipStreamSynchronize(p->stream);
+  for (auto& s : p->ring) {
+    if (s.done) (void)hipEventSynchronize(s.done);
+    if (s.host) (void)hipHostFree(s.host);
+    if (s.dev) (void)hipFree(s.dev);
+    if (s.done) (void)hipEventDestroy(s.done);
+  }
+  (void)hipFree(p->arena);
+  (void)hipFree(p->glinks);
+  (void)hipFree(p->flags);
+  (void)hipFree(p->hooked);
+  (void)hipFree(p->ctl);
+  delete p;
+  return CC_OK;
+}
+
+extern "C" int cc_pool_set_stream(cc_pool* p, void* stream) {
+  if (!p) return CC_EINVAL;
+  p->stream = (hipStream_t)stream;
+  return CC_OK;
+}
+
+extern "C" int cc_pool_set_option(cc_pool* p, int key, int64_t value) {
+  if (!p) return CC_EINVAL;
+  if (key == CC_OPT_UPDATE_MODE || key == CC_OPT_COMPRESS_EVERY) {
+    cc_set_error("cc_pool_set_option: option %d does not apply to pools", key);
+    return CC_EINVAL;
+  }
+  if (key == CC_OPT_HOOK) {
+    for (const auto& g : p->graphs)
+      if (g.used) {
+        cc_set_error("cc_pool_set_option: the linking order is fixed once a graph exists");
+        return CC_EINVAL;
+      }
+  }
+  if (!cc::set_tuning(&p->tune, key, value)) {
+    cc_set_error("cc_pool_set_option: key %d value %lld rejected", key, (long long)value);
+    return CC_EINVAL;
+  }
+  return CC_OK;
+}
+
+extern "C" int cc_pool_add(cc_pool* p, int64_t n, int32_t* id) {
+  if (!p || !id || n < 1) return CC_EINVAL;
+  DeviceGuard dg(p->device);
+  int32_t slot = -1;
+  for (int32_t i = 0; i < p->max_graphs; ++i)
+    if (!p->graphs[(size_t)i].used) {
+      slot = i;
+      break;
+    }
+  if (slot < 0) {
+    cc_set_error("cc_pool_add: all %d graph handles in use", p->max_graphs);
+    return CC_ENOMEM;
+  }
+  const int64_t base = take_gap(p, n);
+  if (base < 0) {
+    cc_set_error("cc_pool_add: no free range of %lld vertices", (long long)n);
+    return CC_ENOMEM;
+  }
+  PoolGraph& g = p->graphs[(size_t)slot];
+  g.base = base;
+  g.n = n;
+  g.used = true;
+  hipLaunchKernelGGL(k_init_range, dim3(blocks_for(n, 256, 4096)), dim3(256), 0, p->stream, p->arena,
+                     (int32_t)base, (int32_t)n);
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, p->stream, p->glinks + (size_t)slot * kPoolLinkStride, 1);
+  HIP_TRY(hipGetLastError());
+  *id = slot;
+  return CC_OK;
+}
+
+extern "C" int cc_pool_remove(cc_pool* p, int32_t id) {
+  if (!valid_graph(p, id)) return CC_EINVAL;
+  PoolGraph& g = p->graphs[(size_t)id];
+  give_gap(p, g.base, g.n);
+  g = PoolGraph();
+  return CC_OK;
+}
+
+extern "C" int cc_pool_reset(cc_pool* p, int32_t id) {
+  if (!valid_graph(p, id)) return CC_EINVAL;
+  DeviceGuard dg(p->device);
+  const PoolGraph& g = p->graphs[(size_t)id];
+  hipLaunchKernelGGL(k_init_range, dim3(blocks_for(g.n, 256, 4096)), dim3(256), 0, p->stream, p->arena,
+                     (int32_t)g.base, (int32_t)g.n);
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, p->stream, p->glinks + (size_t)id * kPoolLinkStride, 1);
+  HIP_TRY(hipGetLastError());
+  return CC_OK;
+}
+
+extern "C" int cc_pool_reset_all(cc_pool* p) {
+  if (!p) return CC_EINVAL;
+  DeviceGuard dg(p->device);
+  hipLaunchKernelGGL(k_init, dim3(blocks_for((p->capacity + 3) / 4, 256, 4096)), dim3(256), 0, p->stream, p->arena,
+                     p->capacity);
+  hipLaunchKernelGGL(k_zero_u64, dim3(64), dim3(256), 0, p->stream, p->glinks, p->max_graphs * kPoolLinkStride);
+  HIP_TRY(hipGetLastError());
+  return CC_OK;
+}
+
+extern "C" int64_t cc_pool_graph_vertices(const cc_pool* p, int32_t id) {
+  return valid_graph(p, id) ? p->graphs[(size_t)id].n : 0;
+}
+
+extern "C" int64_t cc_pool_free_vertices(const cc_pool* p) {
+  if (!p) return 0;
+  int64_t s = 0;
+  for (const auto& kv : p->gaps) s += kv.second;
+  return s;
+}
+
+extern "C" int64_t cc_pool_largest_gap(const cc_pool* p) {
+  if (!p) return 0;
+  int64_t s = 0;
+  for (const auto& kv : p->gaps) s = std::max(s, kv.second);
+  return s;
+}
+
+extern "C" int cc_pool_run(cc_pool* p, const cc_op* ops, int32_t num_ops) {
+  if (!p || num_ops < 0 || (num_ops > 0 && !ops)) return CC_EINVAL;
+  // validate everything first
+  std::vector<int32_t> round(num_ops > 0 ? (size_t)num_ops : 1);
+  std::vector<int32_t> seen((size_t)p->max_graphs, 0);
+  int32_t rounds = 0;
+  int64_t live = 0;
+  for (int32_t i = 0; i < num_ops; ++i) {
+    const cc_op& o = ops[i];
+    if (!valid_graph(p, o.graph) || (o.kind != 0 && o.kind != 1) || o.count < 0 ||
+        (o.count > 0 && (!o.items || (o.kind == 1 && !o.out)))) {
+      cc_set_error("cc_pool_run: operation %d is invalid", i);
+      return CC_EINVAL;
+    }
+    round[(size_t)i] = seen[(size_t)o.graph]++;
+    rounds = std::max(rounds, round[(size_t)i] + 1);
+    live += o.count > 0;
+  }
+  if (live == 0) return CC_OK;
+  DeviceGuard dg(p->device);
+  RingSlot* slot = nullptr;
+  int rc = reserve_slot(p, live, &slot);
+  if (rc != CC_OK) return rc;
+  const int B = p->tune.block;
+  // lay the descriptors out round by round; each round gets its own items per thread
+  std::vector<int64_t> rstart((size_t)rounds + 1, 0), ritems((size_t)rounds, 0), rcount((size_t)rounds, 0);
+  std::vector<bool> rupd((size_t)rounds, false);
+  for (int32_t i = 0; i < num_ops; ++i) {
+    if (ops[i].count == 0) continue;
+    const int r = round[(size_t)i];
+    rcount[(size_t)r]++;
+    ritems[(size_t)r] += ops[i].count;
+    if (ops[i].kind == 0) rupd[(size_t)r] = true;
+  }
+  for (int r = 0; r < rounds; ++r) rstart[(size_t)r + 1] = rstart[(size_t)r] + rcount[(size_t)r];
+  std::vector<int64_t> fill(rstart.begin(), rstart.end() - 1);
+  std::vector<int> ritem_per_thread((size_t)rounds);
+  std::vector<uint32_t> rtiles((size_t)rounds, 0);
+  for (int r = 0; r < rounds; ++r) ritem_per_thread[(size_t)r] = cc::pick_items(p->tune.items, ritems[(size_t)r], B);
+  for (int32_t i = 0; i < num_ops; ++i) {
+    const cc_op& o = ops[i];
+    if (o.count == 0) continue;
+    const int r = round[(size_t)i];
+    const PoolGraph& g = p->graphs[(size_t)o.graph];
+    const int64_t tile = (int64_t)B * ritem_per_thread[(size_t)r];
+    OpDesc& d = slot->host[fill[(size_t)r]++];
+    d.items = reinterpret_cast<const int2*>(o.items);
+    d.out = o.out;
+    d.count = o.count;
+    d.base = (int32_t)g.base;
+    d.n = (int32_t)g.n;
+    d.kind = o.kind;
+    d.graph = o.graph;
+    d.tile0 = rtiles[(size_t)r];
+    d.pad = 0;
+    const int64_t nt = (o.count + tile - 1) / tile;
+    if ((int64_t)rtiles[(size_t)r] + nt > 0xffffffffLL) {
+      cc_set_error("cc_pool_run: too many tiles in one round");
+      return CC_EINVAL;
+    }
+    rtiles[(size_t)r] += (uint32_t)nt;
+  }
+  HIP_TRY(hipMemcpyAsync(slot->dev, slot->host, (size_t)live * sizeof(OpDesc), hipMemcpyHostToDevice, p->stream));
+  for (int r = 0; r < rounds; ++r) {
+    if (rcount[(size_t)r] == 0) continue;
+    const bool record = rupd[(size_t)r] && p->tune.compress_linked;
+    launch_phase(p, ritem_per_thread[(size_t)r], slot->dev + rstart[(size_t)r], (int)rcount[(size_t)r],
+                 rtiles[(size_t)r], record);
+    if (record)
+      hipLaunchKernelGGL(k_compress_hooked, dim3(1024), dim3(256), 0, p->stream, p->arena, p->hooked, p->ctl,
+                         (int32_t)std::min<int64_t>(p->capacity, 0x7fffffff), p->flags);
+  }
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipEventRecord(slot->done, p->stream));
+  slot->pending = true;
+  return CC_OK;
+}
+
+extern "C" int cc_pool_labels(cc_pool* p, int32_t id, int32_t* out) {
+  if (!valid_graph(p, id) || !out) return CC_EINVAL;
+  DeviceGuard dg(p->device);
+  const PoolGraph& g = p->graphs[(size_t)id];
+  const unsigned blocks = blocks_for(g.n, 256, 4096);
+  const int32_t base = (int32_t)g.base, n = (int32_t)g.n;
+  if (p->tune.hook == 1) {
+    hipLaunchKernelGGL(k_fill_i32, dim3(blocks), dim3(256), 0, p->stream, out, n, n);
+    hipLaunchKernelGGL(k_pool_labels_min, dim3(blocks), dim3(256), 0, p->stream, p->arena, base, n, out, p->flags);
+    hipLaunchKernelGGL(k_pool_labels_gather, dim3(blocks), dim3(256), 0, p->stream, p->arena, base, n, out,
+                       p->flags);
+  } else {
+    hipLaunchKernelGGL(k_pool_labels_id, dim3(blocks), dim3(256), 0, p->stream, p->arena, base, n, out, p->flags);
+  }
+  HIP_TRY(hipGetLastError());
+  return CC_OK;
+}
+
+namespace {
+int read_graph_links(cc_pool* p, int32_t id, unsigned long long* links) {
+  HIP_TRY(hipMemcpyAsync(links, p->glinks + (size_t)id * kPoolLinkStride, 8, hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  return CC_OK;
+}
+}  // namespace
+
+extern "C" int cc_pool_num_components(cc_pool* p, int32_t id, int64_t* out) {
+  if (!valid_graph(p, id) || !out) return CC_EINVAL;
+  DeviceGuard dg(p->device);
+  unsigned long long links = 0;
+  int rc = read_graph_links(p, id, &links);
+  if (rc != CC_OK) return rc;
+  *out = p->graphs[(size_t)id].n - (int64_t)links;
+  return CC_OK;
+}
+
+extern "C" int cc_pool_sync(cc_pool* p) {
+  if (!p) return CC_EINVAL;
+  DeviceGuard dg(p->device);
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  int f = 0;
+  HIP_TRY(hipMemcpyAsync(&f, p->flags, sizeof(int), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  if (f) {
+    HIP_TRY(hipMemsetAsync(p->flags, 0, sizeof(int), p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+  }
+  if (f & kFlagCorrupt) {
+    cc_set_error("a find exceeded n steps: a forest in the pool holds a cycle");
+    return CC_ECORRUPT;
+  }
+  if (f & kFlagRange) {
+    cc_set_error("an edge or pair held a vertex id outside its graph; it was skipped");
+    return CC_ERANGE;
+  }
+  return CC_OK;
+}
+
+extern "C" int64_t cc_pool_state_bytes(const cc_pool* p, int32_t id) {
+  return valid_graph(p, id) ? 16 + 4 * p->graphs[(size_t)id].n : 0;
+}
+
+extern "C" int cc_pool_save(cc_pool* p, int32_t id, void* host_buf) {
+  if (!valid_graph(p, id) || !host_buf) return CC_EINVAL;
+  DeviceGuard dg(p->device);
+  const PoolGraph& g = p->graphs[(size_t)id];
+  unsigned long long links = 0;
+  int rc = read_graph_links(p, id, &links);
+  if (rc != CC_OK) return rc;
+  int64_t hdr[2] = {g.n, (int64_t)links};
+  memcpy(host_buf, hdr, 16);
+  int32_t* par = reinterpret_cast<int32_t*>((char*)host_buf + 16);
+  HIP_TRY(hipMemcpyAsync(par, p->arena + g.base, (size_t)g.n * 4, hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  const int32_t base = (int32_t)g.base;
+  for (int64_t v = 0; v < g.n; ++v) par[v] -= base;
+  return CC_OK;
+}
+
+extern "C" int cc_pool_load(cc_pool* p, int32_t id, const void* host_buf) {
+  if (!valid_graph(p, id) || !host_buf) return CC_EINVAL;
+  DeviceGuard dg(p->device);
+  const PoolGraph& g = p->graphs[(size_t)id];
+  int64_t hdr[2];
+  memcpy(hdr, host_buf, 16);
+  if (hdr[0] != g.n) {
+    cc_set_error("cc_pool_load: image has n=%lld, graph has n=%lld", (long long)hdr[0], (long long)g.n);
+    return CC_EINVAL;
+  }
+  const int32_t* par = reinterpret_cast<const int32_t*>((const char*)host_buf + 16);
+  int64_t roots = 0;
+  if (!cc::check_forest(par, g.n, p->tune.hook, &roots) || hdr[1] != g.n - roots) {
+    cc_set_error("cc_pool_load: image is not a forest under the pool's linking order");
+    return CC_ECORRUPT;
+  }
+  int32_t* staging = nullptr;
+  HIP_TRY(hipHostMalloc((void**)&staging, (size_t)g.n * 4, hipHostMallocDefault));
+  const int32_t base = (int32_t)g.base;
+  for (int64_t v = 0; v < g.n; ++v) staging[v] = par[v] + base;
+  unsigned long long links = (unsigned long long)hdr[1];
+  hipError_t e = hipStreamSynchronize(p->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(p->arena + g.base, staging, (size_t)g.n * 4, hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(p->glinks + (size_t)id * kPoolLinkStride, &links, 8, hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  (void)hipHostFree(staging);
+  if (e != hipSuccess) {
+    cc_set_error("cc_pool_load: %s", hipGetErrorString(e));
+    return CC_EDEVICE;
+  }
+  return CC_OK;
+}

@@ -1,0 +1,158 @@
+// Kernels of the many-graph form: independent graphs share one parent arena
+// (graph g owns ids [base_g, base_g + n_g) and its parent entries hold arena
+// ids), and one launch runs one operation per graph for many graphs at once.
+//
+// A launch is a list of op descriptors; op i covers tiles [tile0_i,
+// tile0_i + ntiles_i) of the launch's tile space, a tile being blockDim.x *
+// ITEMS items.  Each block walks tiles grid-stride and looks its op up by
+// binary search, so graphs of very different sizes share the grid without
+// one launch per graph.  Updates and queries may be mixed in one launch:
+// they touch different graphs.
+#pragma once
+
+#include "cc_kernels.hpp"
+
+namespace ccdev {
+namespace {  // kernels get internal linkage in every translation unit
+
+constexpr int kPoolLinkStride = 16;  // per-graph link counters 128 B apart
+
+struct OpDesc {
+  const int2* items;  // edges (update) or pairs (query), graph-local ids
+  uint8_t* out;       // answers (query)
+  int64_t count;
+  int32_t base;       // arena offset of the graph
+  int32_t n;          // vertices of the graph
+  int32_t kind;       // 0 update, 1 query
+  int32_t graph;      // pool slot (link counter index)
+  uint32_t tile0;
+  uint32_t pad;
+};
+
+__device__ __forceinline__ int find_op(const OpDesc* ops, int nops, uint32_t tile) {
+  int lo = 0, hi = nops - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ops[mid].tile0 <= tile) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int block_sum(int v, int* red) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  int s = 0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+  __syncthreads();
+  return s;  // valid in thread 0
+}
+
+template <int ITEMS, bool HASH, bool RECORD, bool HALVE_Q>
+__global__ void k_pool_phase(const OpDesc* __restrict__ ops, int nops, uint32_t ntiles,
+                             int32_t* __restrict__ arena, unsigned long long* __restrict__ glinks,
+                             int* __restrict__ flags, int32_t* __restrict__ hooked,
+                             unsigned* __restrict__ hooked_ctl) {
+  __shared__ int wave_off[16];
+  __shared__ unsigned blk[2];
+  __shared__ int red[16];
+  const uint32_t T = blockDim.x * ITEMS;
+  for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const OpDesc op = ops[find_op(ops, nops, t)];
+    const int64_t t0 = (int64_t)(t - op.tile0) * T;
+    int2 e[ITEMS];
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      const int64_t i = t0 + (int64_t)k * blockDim.x + threadIdx.x;
+      e[k] = i < op.count ? op.items[i] : make_int2(0, 0);
+    }
+    if (op.kind == 0) {
+      int32_t hk[ITEMS];
+      int nh = 0;
+#pragma unroll
+      for (int k = 0; k < ITEMS; ++k) {
+        hk[k] = -1;
+        if (!in_range(e[k], op.n)) {
+          raise_flag(flags, kFlagRange);
+          continue;
+        }
+        if (e[k].x == e[k].y) continue;
+        const int32_t u = op.base + e[k].x, v = op.base + e[k].y;
+        const int32_t pu = ld(arena + u), pv = ld(arena + v);
+        if (pu == pv || pu == v || pv == u) continue;
+        const int32_t ru = find_halve_from(arena, u, pu, op.n, flags);
+        const int32_t rv = find_halve_from(arena, v, pv, op.n, flags);
+        if (ru != rv) {
+          if (HASH) {
+            ByHash o;
+            o.base = op.base;
+            hk[k] = link_roots(arena, ru, rv, op.n, flags, o);
+          } else {
+            hk[k] = link_roots(arena, ru, rv, op.n, flags, ById{});
+          }
+          if (hk[k] >= 0) ++nh;
+        }
+      }
+      const int links = block_sum(nh, red);
+      if (threadIdx.x == 0 && links > 0)
+        atomicAdd(glinks + (size_t)op.graph * kPoolLinkStride, (unsigned long long)links);
+      if (RECORD) {
+        unsigned pos = block_reserve(nh, hooked_ctl, wave_off, blk);
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k)
+          if (hk[k] >= 0) hooked[pos++] = hk[k];
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < ITEMS; ++k) {
+        const int64_t i = t0 + (int64_t)k * blockDim.x + threadIdx.x;
+        uint8_t a = 0;
+        if (!in_range(e[k], op.n)) {
+          raise_flag(flags, kFlagRange);
+        } else if (e[k].x == e[k].y) {
+          a = 1;
+        } else {
+          const int32_t ru = find_root<HALVE_Q>(arena, op.base + e[k].x, op.n, flags);
+          const int32_t rv = find_root<HALVE_Q>(arena, op.base + e[k].y, op.n, flags);
+          a = ru == rv;
+        }
+        if (i < op.count) op.out[i] = a;
+      }
+    }
+  }
+}
+
+__global__ void k_init_range(int32_t* __restrict__ arena, int32_t base, int32_t n) {
+  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+    arena[base + v] = base + v;
+}
+
+// Labels of one pool graph, graph-local: id order (root = minimum).
+__global__ void k_pool_labels_id(int32_t* __restrict__ arena, int32_t base, int32_t n, int32_t* __restrict__ out,
+                                 int* __restrict__ flags) {
+  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+    const int32_t r = find_halve(arena, base + v, n, flags);
+    if (ld(arena + base + v) != r) st(arena + base + v, r);
+    out[v] = r - base;
+  }
+}
+
+// Hashed order: minimum id per root (out pre-filled with n), then a gather.
+__global__ void k_pool_labels_min(int32_t* __restrict__ arena, int32_t base, int32_t n, int32_t* __restrict__ out,
+                                  int* __restrict__ flags) {
+  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+    const int32_t r = find_halve(arena, base + v, n, flags);
+    if (ld(arena + base + v) != r) st(arena + base + v, r);
+    atomicMin(out + (r - base), v);
+  }
+}
+
+__global__ void k_pool_labels_gather(const int32_t* __restrict__ arena, int32_t base, int32_t n,
+                                     int32_t* __restrict__ out, int* __restrict__ flags) {
+  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+    out[v] = out[find_read(arena, base + v, n, flags) - base];
+}
+
+}  // namespace
+}  // namespace ccdev

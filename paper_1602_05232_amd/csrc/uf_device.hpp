@@ -66,13 +66,16 @@ __device__ __forceinline__ uint32_t fmix32(uint32_t h) {
 }
 
 // Linking orders: above(a, b) is true when a outranks b, i.e. b may be
-// linked under a.
+// linked under a.  Ids may carry an offset `base` (many graphs in one array);
+// the order is that of the graph-local ids, so it does not depend on where a
+// graph sits.
 struct ById {
-  static __device__ __forceinline__ bool above(int32_t a, int32_t b) { return a < b; }
+  __device__ __forceinline__ bool above(int32_t a, int32_t b) const { return a < b; }
 };
 struct ByHash {
-  static __device__ __forceinline__ bool above(int32_t a, int32_t b) {
-    return fmix32((uint32_t)a) < fmix32((uint32_t)b);
+  int32_t base = 0;
+  __device__ __forceinline__ bool above(int32_t a, int32_t b) const {
+    return fmix32((uint32_t)(a - base)) < fmix32((uint32_t)(b - base));
   }
 };
 
@@ -125,10 +128,10 @@ __device__ __forceinline__ int32_t find_root(int32_t* parent, int32_t x, int32_t
 // were already one.
 template <class Ord>
 __device__ __forceinline__ int32_t link_roots(int32_t* parent, int32_t a, int32_t b, int32_t cap,
-                                              int* flags) {
+                                              int* flags, const Ord& ord) {
   int32_t steps = 0;
   while (a != b) {
-    const bool a_wins = Ord::above(a, b);
+    const bool a_wins = ord.above(a, b);
     const int32_t hi = a_wins ? b : a;  // loses: gets linked under the other
     const int32_t lo = a_wins ? a : b;
     const int32_t old = cas(parent + hi, hi, lo);

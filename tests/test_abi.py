@@ -24,7 +24,7 @@ def libcc():
     return ctypes.CDLL(hipbuild.OUT)
 
 
-@pytest.mark.parametrize("header", ["cc.h", "cc_bench.h"])
+@pytest.mark.parametrize("header", ["cc.h", "cc_pool.h", "cc_bench.h"])
 def test_exports_every_declared_symbol(libcc, header):
     names = declared_functions(header)
     assert len(names) >= 4
@@ -36,6 +36,7 @@ def test_binding_declares_every_symbol():
     from paper_1602_05232_amd import cc
     assert set(declared_functions("cc.h")) == set(cc.SIGNATURES)
     assert set(declared_functions("cc_bench.h")) == set(cc.BENCH_SIGNATURES)
+    assert set(declared_functions("cc_pool.h")) == set(cc.POOL_SIGNATURES)
 
 
 def test_strerror_and_invalid_args_without_device(libcc):

@@ -1,0 +1,91 @@
+"""Captured (HIP graph) update/query sequences replay to the eager results.
+
+Each replay is checked against the eager run, with other eager work and
+host synchronisations between replays."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1602_05232_amd as ccgpu
+    ccgpu.lib()
+    return ccgpu
+
+
+@pytest.mark.parametrize("opts", [dict(), dict(update_mode=1), dict(hook=1), dict(compress_linked=0, items=1)],
+                         ids=lambda o: ",".join("%s=%s" % kv for kv in sorted(o.items())) or "default")
+def test_capture_replays_match_eager(cc, opts):
+    s = synth.grid_stream_cfg(W=128, H=128, batch=1 << 10, qbatch=1 << 8)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        E = torch.from_numpy(s.edges).cuda()
+        Q = torch.from_numpy(s.queries).cuda()
+        out_e = torch.empty(len(s.queries), dtype=torch.uint8, device="cuda")
+        out_g = torch.empty_like(out_e)
+        lab_e = torch.empty(s.n, dtype=torch.int32, device="cuda")
+        lab_g = torch.empty_like(lab_e)
+        g = cc.Graph(s.n, stream=st, **opts)
+        g.reserve(int(np.diff(s.eoff).max()))
+
+        def sequence(out, lab):
+            g.reset()
+            for i in range(s.num_batches):
+                g.bulk_update(E[s.eoff[i]:s.eoff[i + 1]])
+                g.bulk_query(Q[s.qoff[i]:s.qoff[i + 1]], out=out[s.qoff[i]:s.qoff[i + 1]])
+            g.labels(out=lab)
+
+        sequence(out_e, lab_e)
+        st.synchronize()
+        comps = g.num_components()
+        with g.capture() as cap:
+            sequence(out_g, lab_g)
+        rec = cap.recording
+        ref = oracle.UnionFind(s.n)
+        want = np.concatenate([(ref.bulk_update(s.batch(i)), ref.bulk_query(s.query(i)))[1]
+                               for i in range(s.num_batches)])
+        np.testing.assert_array_equal(out_e.cpu().numpy(), want)
+        np.testing.assert_array_equal(lab_e.cpu().numpy(), ref.labels())
+        other = cc.Graph(1000, stream=st)
+        for rep in range(3):
+            out_g.fill_(7)
+            lab_g.fill_(-1)
+            other.bulk_update(torch.randint(0, 1000, (500, 2), dtype=torch.int32, device="cuda"))
+            st.synchronize()
+            rec.launch()
+            st.synchronize()
+            np.testing.assert_array_equal(out_g.cpu().numpy(), out_e.cpu().numpy(), err_msg="replay %d" % rep)
+            np.testing.assert_array_equal(lab_g.cpu().numpy(), lab_e.cpu().numpy(), err_msg="replay %d" % rep)
+            assert g.num_components() == comps
+            assert g.sync() == cc.cc.CC_OK
+        rec.close()
+        other.close()
+        g.close()
+
+
+def test_capture_rejects_waiting_calls(cc):
+    st = torch.cuda.Stream()
+    g = cc.Graph(100, stream=st)
+    L = cc.lib()
+    import ctypes
+    assert L.cc_capture_begin(g.handle) == 0
+    v = ctypes.c_int64()
+    assert L.cc_num_components(g.handle, ctypes.byref(v)) == cc.cc.CC_EINVAL
+    assert L.cc_sync(g.handle) == cc.cc.CC_EINVAL
+    assert L.cc_capture_begin(g.handle) == cc.cc.CC_EINVAL
+    x = ctypes.c_void_p()
+    assert L.cc_capture_end(g.handle, ctypes.byref(x)) == 0
+    assert L.cc_exec_destroy(x.value) == 0
+    g0 = cc.Graph(10, stream=torch.cuda.default_stream())
+    if g0.stream.cuda_stream == 0:
+        assert L.cc_capture_begin(g0.handle) == cc.cc.CC_EINVAL
+    g0.close()
+    g.close()

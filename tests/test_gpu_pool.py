@@ -1,0 +1,134 @@
+"""The many-graph pool (batched form) against one oracle per graph."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1602_05232_amd as ccgpu
+    ccgpu.lib()
+    return ccgpu
+
+
+def dev(a):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+    return torch.from_numpy(a).cuda()
+
+
+def small_graphs(G, seed=5):
+    """Graphs of the many-graph recipe, with sizes scaled down for the oracle."""
+    ns = synth.multi_graph_sizes(G=G, mu=9.0, sigma=2.0, lo=1 << 4, hi=1 << 13, seed=seed)
+    return [synth.multi_graph_stream(g, int(ns[g]), qbatch=200, rmat_from=G // 2, seed=seed) for g in range(G)]
+
+
+@pytest.mark.parametrize("opts", [dict(), dict(hook=1), dict(items=1, block=64, grid_cap=5),
+                                  dict(items=8, block=512, compress_linked=0, query_halving=0)],
+                         ids=lambda o: ",".join("%s=%s" % kv for kv in sorted(o.items())) or "default")
+def test_pool_steps_match_oracle(cc, opts):
+    G = 96
+    streams = small_graphs(G)
+    pool = cc.Pool(sum(s.n for s in streams) + 1000, G + 4, **opts)
+    ids = [pool.add(s.n) for s in streams]
+    refs = [oracle.UnionFind(s.n) for s in streams]
+    E = [dev(s.edges) for s in streams]
+    Q = [dev(s.queries) for s in streams]
+    outs = [torch.empty(len(s.queries), dtype=torch.uint8, device="cuda") for s in streams]
+    for step in range(4):
+        ops = []
+        for g, s in enumerate(streams):
+            e0, e1 = int(s.eoff[step]), int(s.eoff[step + 1])
+            q0, q1 = int(s.qoff[step]), int(s.qoff[step + 1])
+            ops.append((ids[g], cc.UPDATE, E[g][e0:e1], None))
+        for g, s in enumerate(streams):
+            q0, q1 = int(s.qoff[step]), int(s.qoff[step + 1])
+            ops.append((ids[g], cc.QUERY, Q[g][q0:q1], outs[g][q0:q1]))
+        pool.run(ops)
+    for g, s in enumerate(streams):
+        want = []
+        for k in range(4):
+            refs[g].bulk_update(s.batch(k))
+            want.append(refs[g].bulk_query(s.query(k)))
+        np.testing.assert_array_equal(outs[g].cpu().numpy(), np.concatenate(want), err_msg="graph %d" % g)
+        np.testing.assert_array_equal(pool.labels(ids[g]).cpu().numpy(), refs[g].labels(), err_msg="graph %d" % g)
+        assert pool.num_components(ids[g]) == refs[g].num_components()
+    assert pool.sync() == cc.cc.CC_OK
+    pool.close()
+
+
+def test_pool_many_rounds_in_one_run(cc):
+    # several operations per graph in one run: rounds must keep list order
+    G = 24
+    streams = small_graphs(G, seed=9)
+    pool = cc.Pool(sum(s.n for s in streams), G)
+    ids = [pool.add(s.n) for s in streams]
+    ops, outs, want = [], [], []
+    for g, s in enumerate(streams):
+        ref = oracle.UnionFind(s.n)
+        for k in range(4):
+            ops.append((ids[g], cc.UPDATE, dev(s.batch(k)), None))
+            ref.bulk_update(s.batch(k))
+            o = torch.empty(len(s.query(k)), dtype=torch.uint8, device="cuda")
+            ops.append((ids[g], cc.QUERY, dev(s.query(k)), o))
+            outs.append(o)
+            want.append(ref.bulk_query(s.query(k)))
+    # interleave graphs so that consecutive list entries belong to different graphs
+    order = sorted(range(len(ops)), key=lambda i: (i % 8, i))
+    per_graph = {}
+    for i in order:
+        per_graph.setdefault(ops[i][0], []).append(i)
+    assert all(v == sorted(v) for v in per_graph.values())
+    pool.run([ops[i] for i in order])
+    for o, w in zip(outs, want):
+        np.testing.assert_array_equal(o.cpu().numpy(), w)
+    pool.close()
+
+
+def test_pool_gaps_eviction_and_images(cc):
+    pool = cc.Pool(10000, 8)
+    a = pool.add(4000)
+    b = pool.add(3000)
+    c = pool.add(3000)
+    assert pool.free_vertices() == 0
+    with pytest.raises(cc.CCError) as ei:
+        pool.add(1)
+    assert ei.value.code == cc.cc.CC_ENOMEM
+    s = synth.rmat_stream(scale=11, size_lo=6, size_hi=10, qbatch=64)  # n = 2048 <= 3000
+    eb = synth.uniform_pairs(synth.key(3, 0, 1), 0, 5000, 3000)
+    pool.run([(b, cc.UPDATE, dev(eb), None)])
+    ref = oracle.UnionFind(3000)
+    ref.bulk_update(eb)
+    img = pool.save(b)  # evict b
+    pool.remove(b)
+    assert pool.largest_gap() == 3000
+    d = pool.add(2048)  # another graph takes part of the gap
+    pool.run([(d, cc.UPDATE, dev(s.edges), None)])
+    with pytest.raises(cc.CCError):
+        pool.add(3000)  # no room for b any more
+    pool.remove(d)
+    b2 = pool.add(3000)  # restore b elsewhere
+    pool.load(b2, img)
+    np.testing.assert_array_equal(pool.labels(b2).cpu().numpy(), ref.labels())
+    assert pool.num_components(b2) == ref.num_components()
+    # the image is a cc_save image: a standalone graph takes it as is
+    g = cc.Graph(3000)
+    g.load(img)
+    np.testing.assert_array_equal(g.labels().cpu().numpy(), ref.labels())
+    g.close()
+    # invalid operations are rejected before anything runs
+    with pytest.raises(cc.CCError) as ei:
+        pool.run([(a, cc.UPDATE, dev(eb[:10]), None), (77, cc.UPDATE, dev(eb[:10]), None)])
+    assert ei.value.code == cc.cc.CC_EINVAL
+    assert pool.num_components(a) == 4000
+    # out-of-range ids are skipped and reported
+    pool.run([(c, cc.UPDATE, dev([[0, 1], [2, 3000], [5, 6]]), None)])
+    assert pool.sync() == cc.cc.CC_ERANGE
+    assert pool.num_components(c) == 3000 - 2
+    pool.close()
