@@ -15,7 +15,9 @@ Other workloads compare the forms of the path on their own configurations:
                followed by 2^10 queries: plain launches vs one HIP-graph replay
   batched1024  1024 independent graphs (log-normal sizes): one launch per
                graph and operation vs the pool's one launch per round
-  serve64      see serve.py (request loop over 64 R-MAT scale-22 graphs)
+  serve64      request loop over 64 R-MAT scale-22 graphs, Poisson arrivals of
+               70% updates / 30% queries: continuous batching vs serial plain,
+               saturation throughput and p50/p99 latency
 
 Prints ONE JSON line.  `value` is (update edges + query pairs) per second of
 wall clock over the timed steps.
@@ -44,10 +46,14 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# sources of the plain update kernels: a change to any of them voids stored counter readings
+KERNEL_SOURCES = ("uf_device.hpp", "cc_kernels.hpp", "cc_plain.hip", "cc_internal.hpp")
+
+
 def source_digest() -> str:
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1602_05232_amd", "csrc")
-    for f in sorted(os.listdir(d)):
+    for f in KERNEL_SOURCES:
         with open(os.path.join(d, f), "rb") as fh:
             h.update(f.encode() + b"\0" + fh.read())
     return h.hexdigest()[:16]
@@ -379,12 +385,107 @@ def run_batched(args):
     return res
 
 
+def run_serve(args):
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1602_05232_amd import serve, tuning
+
+    S, scale, R = 64, args.serve_scale, args.requests
+    n = 1 << scale
+    seed = synth.BASE_SEED + 5
+    t = time.perf_counter()
+    kind_u = synth.unit_doubles(synth.key(seed, 0, synth.P_REQ_TYPE), 0, R)
+    strm = (synth.unit_doubles(synth.key(seed, 0, synth.P_REQ_STREAM), 0, R) * S).astype(np.int64)
+    sizes = np.floor(np.exp2(8 + 14 * synth.unit_doubles(synth.key(seed, 0, synth.P_REQ_SIZE), 0, R))).astype(np.int64)
+    perms = {}
+    cursor = np.zeros(S, np.int64)
+    reqs = []
+    tot_e = tot_q = 0
+    for i in range(R):
+        st, size = int(strm[i]), int(sizes[i])
+        if kind_u[i] < 0.7:
+            if st not in perms:
+                perms[st] = synth.permutation(synth.key(seed, st + 1, synth.P_PERM), n)
+            items = synth.rmat_edges(synth.key(seed, st + 1, synth.P_EDGES), int(cursor[st]), size, scale, n,
+                                     perms[st])
+            cursor[st] += size
+            reqs.append(serve.Request(i, st, serve.UPDATE, 0.0, torch.from_numpy(items).cuda(), None, size))
+            tot_e += size
+        else:
+            items = synth.uniform_pairs(synth.key(seed, st + 1, synth.P_QUERIES), i, size, n)
+            reqs.append(serve.Request(i, st, serve.QUERY, 0.0, torch.from_numpy(items).cuda(),
+                                      torch.zeros(size, dtype=torch.uint8, device="cuda"), size))
+            tot_q += size
+    torch.cuda.synchronize()
+    log("serving trace: %d requests over %d streams of n=2^%d, %d update edges, %d query pairs (%.1fs)"
+        % (R, S, scale, tot_e, tot_q, time.perf_counter() - t))
+    popts = tuning.lookup("pool", "mixed", n) or {}
+    popts = {k: v for k, v in popts.items() if k not in ("update_mode", "compress_every")}
+    popts["compress_linked"] = 0  # rounds overlap on two streams
+
+    def with_arrivals(times):
+        out = []
+        for r, a in zip(reqs, times):
+            o = None if r.out is None else torch.zeros_like(r.out)
+            out.append(serve.Request(r.rid, r.stream, r.kind, float(a), r.items, o, r.size))
+        return out
+
+    def run(form, times, budget):
+        ex = serve.GpuExecutor(budget, S + 1, **popts)
+        sch = serve.serial_scheduler(ex, [n] * S) if form == "serial" else serve.Scheduler(ex, [n] * S, 2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        done = sch.run(with_arrivals(times))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        answers = {r.rid: r.out for r in done if r.kind == serve.QUERY}
+        info = {"wall_s": wall, "items_per_s": (tot_e + tot_q) / wall, "rounds": sch.rounds,
+                "mean_round_size": float(np.mean(sch.round_sizes)), "evictions": sch.evictions}
+        info.update(serve.latency_summary(done))
+        assert ex.pool.sync() == 0
+        ex.close()
+        log("%s: %s" % (form, info))
+        return info, answers
+
+    zeros = np.zeros(R)
+    full = S * n
+    for _ in range(args.warmup):
+        run("served", zeros, full)
+    sat_served, a1 = run("served", zeros, full)
+    sat_serial, a2 = run("serial", zeros, full)
+    for rid in a1:
+        assert torch.equal(a1[rid], a2[rid]), "served and serial answers differ"
+    # latency at 70% of the serial form's capacity (requests per second)
+    lam = 0.7 * R / sat_serial["wall_s"]
+    arr = synth.poisson_arrivals(synth.key(seed, 0, synth.P_ARRIVALS), R, lam)
+    lat_served, _ = run("served", arr, full)
+    lat_serial, _ = run("serial", arr, full)
+    budget = (256 << 20) // 4  # 256 MiB of parent entries: a quarter of the graphs resident
+    lat_evict, a3 = run("served", arr, budget)
+    for rid in a1:
+        assert torch.equal(a1[rid], a3[rid]), "answers changed under eviction"
+    res = result((tot_e + tot_q) / sat_served["wall_s"], 1, args.warmup, sat_served["wall_s"], {
+        "workload": "serve%d-rmat%d" % (S, scale), "streams": S, "n_per_stream": n, "requests": R,
+        "update_fraction": 0.7, "request_sizes": "floor(2^U), U ~ U[8, 22]", "update_edges": tot_e,
+        "query_pairs": tot_q, "form": "served (continuous batching, 2 HIP streams)", "options": popts})
+    res.update({"saturation": {"served": sat_served, "serial": sat_serial,
+                               "speedup": sat_serial["wall_s"] / sat_served["wall_s"]},
+                "poisson_rate_per_s": lam,
+                "latency_at_0.7_serial_capacity": {"served": lat_served, "serial": lat_serial},
+                "latency_with_256MiB_budget": lat_evict})
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rmat24", choices=["rmat24", "grid4096", "batched1024"])
+    ap.add_argument("--workload", default="rmat24", choices=["rmat24", "grid4096", "batched1024", "serve64"])
+    ap.add_argument("--requests", type=int, default=1024, help="requests of the serving trace")
+    ap.add_argument("--serve-scale", type=int, default=22, help="R-MAT scale of each served graph")
     ap.add_argument("--scale", type=int, default=24, help="R-MAT scale of the rmat24 workload")
     ap.add_argument("--graphs", type=int, default=1024, help="graphs of the batched workload")
     ap.add_argument("--options", default="", help="JSON dict of option overrides")
@@ -403,7 +504,8 @@ def main():
     if not os.path.exists(hipbuild.OUT):
         import __graft_entry__
         __graft_entry__.build()
-    res = {"rmat24": run_rmat, "grid4096": run_grid, "batched1024": run_batched}[args.workload](args)
+    res = {"rmat24": run_rmat, "grid4096": run_grid, "batched1024": run_batched,
+           "serve64": run_serve}[args.workload](args)
     print(json.dumps(res), flush=True)
 
 

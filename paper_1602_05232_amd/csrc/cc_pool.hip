@@ -26,10 +26,15 @@ struct PoolGraph {
   bool used = false;
 };
 
+// One run in flight: its descriptors, and the list of roots its updates
+// linked (compressed after each round).  A slot is reused only after its
+// run has completed, so runs on different streams never share a list.
 struct RingSlot {
   OpDesc* host = nullptr;  // pinned staging
   OpDesc* dev = nullptr;
   int64_t cap = 0;
+  int32_t* hooked = nullptr;  // capacity entries, allocated on first use
+  unsigned* ctl = nullptr;    // [0] hooked count, [1] finished blocks
   hipEvent_t done = nullptr;
   bool pending = false;
 };
@@ -44,8 +49,6 @@ struct cc_pool {
   int32_t* arena = nullptr;
   unsigned long long* glinks = nullptr;  // max_graphs * kPoolLinkStride
   int* flags = nullptr;
-  int32_t* hooked = nullptr;  // capacity entries
-  unsigned* ctl = nullptr;    // [0] hooked count, [1] finished blocks
   std::vector<PoolGraph> graphs;
   std::map<int64_t, int64_t> gaps;  // base -> length of each free range
   RingSlot ring[kRing];
@@ -87,7 +90,7 @@ void give_gap(cc_pool* p, int64_t base, int64_t n) {
   }
 }
 
-int reserve_slot(cc_pool* p, int64_t count, RingSlot** out) {
+int reserve_slot(cc_pool* p, int64_t count, bool record, RingSlot** out) {
   RingSlot* s = &p->ring[p->ring_next];
   p->ring_next = (p->ring_next + 1) % kRing;
   if (s->pending) {
@@ -108,40 +111,49 @@ int reserve_slot(cc_pool* p, int64_t count, RingSlot** out) {
     }
     s->cap = cap;
   }
+  if (record && !s->hooked) {
+    if (hipMalloc((void**)&s->hooked, (size_t)p->capacity * 4) != hipSuccess ||
+        hipMalloc((void**)&s->ctl, 64) != hipSuccess) {
+      cc_set_error("cc_pool_run: hooked-list allocation failed");
+      return CC_ENOMEM;
+    }
+    HIP_TRY(hipMemsetAsync(s->ctl, 0, 64, p->stream));
+  }
   *out = s;
   return CC_OK;
 }
 
 template <int ITEMS, bool HASH, bool RECORD>
-void launch_phase_t(cc_pool* p, const OpDesc* d, int nops, uint32_t ntiles) {
+void launch_phase_t(cc_pool* p, const RingSlot* s, const OpDesc* d, int nops, uint32_t ntiles) {
   const int B = p->tune.block;
   const unsigned grid = (unsigned)std::min<int64_t>(ntiles, p->tune.grid_cap);
   if (p->tune.query_halving)
     hipLaunchKernelGGL((k_pool_phase<ITEMS, HASH, RECORD, true>), dim3(grid), dim3(B), 0, p->stream, d, nops,
-                       ntiles, p->arena, p->glinks, p->flags, p->hooked, p->ctl);
+                       ntiles, p->arena, p->glinks, p->flags, s->hooked, s->ctl);
   else
     hipLaunchKernelGGL((k_pool_phase<ITEMS, HASH, RECORD, false>), dim3(grid), dim3(B), 0, p->stream, d, nops,
-                       ntiles, p->arena, p->glinks, p->flags, p->hooked, p->ctl);
+                       ntiles, p->arena, p->glinks, p->flags, s->hooked, s->ctl);
 }
 
 template <int ITEMS>
-void launch_phase_i(cc_pool* p, const OpDesc* d, int nops, uint32_t ntiles, bool record) {
+void launch_phase_i(cc_pool* p, const RingSlot* s, const OpDesc* d, int nops, uint32_t ntiles, bool record) {
   const bool hash = p->tune.hook == 1;
   if (hash) {
-    if (record) launch_phase_t<ITEMS, true, true>(p, d, nops, ntiles);
-    else launch_phase_t<ITEMS, true, false>(p, d, nops, ntiles);
+    if (record) launch_phase_t<ITEMS, true, true>(p, s, d, nops, ntiles);
+    else launch_phase_t<ITEMS, true, false>(p, s, d, nops, ntiles);
   } else {
-    if (record) launch_phase_t<ITEMS, false, true>(p, d, nops, ntiles);
-    else launch_phase_t<ITEMS, false, false>(p, d, nops, ntiles);
+    if (record) launch_phase_t<ITEMS, false, true>(p, s, d, nops, ntiles);
+    else launch_phase_t<ITEMS, false, false>(p, s, d, nops, ntiles);
   }
 }
 
-void launch_phase(cc_pool* p, int items, const OpDesc* d, int nops, uint32_t ntiles, bool record) {
+void launch_phase(cc_pool* p, const RingSlot* s, int items, const OpDesc* d, int nops, uint32_t ntiles,
+                  bool record) {
   switch (items) {
-    case 1: launch_phase_i<1>(p, d, nops, ntiles, record); break;
-    case 2: launch_phase_i<2>(p, d, nops, ntiles, record); break;
-    case 8: launch_phase_i<8>(p, d, nops, ntiles, record); break;
-    default: launch_phase_i<4>(p, d, nops, ntiles, record); break;
+    case 1: launch_phase_i<1>(p, s, d, nops, ntiles, record); break;
+    case 2: launch_phase_i<2>(p, s, d, nops, ntiles, record); break;
+    case 8: launch_phase_i<8>(p, s, d, nops, ntiles, record); break;
+    default: launch_phase_i<4>(p, s, d, nops, ntiles, record); break;
   }
 }
 
@@ -163,8 +175,6 @@ extern "C" cc_pool* cc_pool_create(int64_t capacity, int32_t max_graphs) {
     (void)hipFree(p->arena);
     (void)hipFree(p->glinks);
     (void)hipFree(p->flags);
-    (void)hipFree(p->hooked);
-    (void)hipFree(p->ctl);
     delete p;
     return nullptr;
   };
@@ -172,10 +182,7 @@ extern "C" cc_pool* cc_pool_create(int64_t capacity, int32_t max_graphs) {
   if (hipMalloc(&p->arena, (size_t)capacity * 4) != hipSuccess) return fail("arena");
   if (hipMalloc(&p->glinks, (size_t)max_graphs * kPoolLinkStride * 8) != hipSuccess) return fail("links");
   if (hipMalloc(&p->flags, 64) != hipSuccess) return fail("flags");
-  if (hipMalloc(&p->hooked, (size_t)capacity * 4) != hipSuccess) return fail("hooked");
-  if (hipMalloc(&p->ctl, 64) != hipSuccess) return fail("ctl");
   if (hipMemsetAsync(p->flags, 0, 64, p->stream) != hipSuccess) return fail("memset");
-  if (hipMemsetAsync(p->ctl, 0, 64, p->stream) != hipSuccess) return fail("memset");
   if (hipMemsetAsync(p->glinks, 0, (size_t)max_graphs * kPoolLinkStride * 8, p->stream) != hipSuccess)
     return fail("memset");
   for (auto& s : p->ring)
@@ -192,13 +199,13 @@ extern "C" int cc_pool_destroy(cc_pool* p) {
     if (s.done) (void)hipEventSynchronize(s.done);
     if (s.host) (void)hipHostFree(s.host);
     if (s.dev) (void)hipFree(s.dev);
+    if (s.hooked) (void)hipFree(s.hooked);
+    if (s.ctl) (void)hipFree(s.ctl);
     if (s.done) (void)hipEventDestroy(s.done);
   }
   (void)hipFree(p->arena);
   (void)hipFree(p->glinks);
   (void)hipFree(p->flags);
-  (void)hipFree(p->hooked);
-  (void)hipFree(p->ctl);
   delete p;
   return CC_OK;
 }
@@ -326,8 +333,10 @@ extern "C" int cc_pool_run(cc_pool* p, const cc_op* ops, int32_t num_ops) {
   }
   if (live == 0) return CC_OK;
   DeviceGuard dg(p->device);
+  bool any_update = false;
+  for (int32_t i = 0; i < num_ops; ++i) any_update |= ops[i].kind == 0 && ops[i].count > 0;
   RingSlot* slot = nullptr;
-  int rc = reserve_slot(p, live, &slot);
+  int rc = reserve_slot(p, live, any_update && p->tune.compress_linked, &slot);
   if (rc != CC_OK) return rc;
   const int B = p->tune.block;
   // lay the descriptors out round by round; each round gets its own items per thread
@@ -372,11 +381,11 @@ extern "C" int cc_pool_run(cc_pool* p, const cc_op* ops, int32_t num_ops) {
   for (int r = 0; r < rounds; ++r) {
     if (rcount[(size_t)r] == 0) continue;
     const bool record = rupd[(size_t)r] && p->tune.compress_linked;
-    launch_phase(p, ritem_per_thread[(size_t)r], slot->dev + rstart[(size_t)r], (int)rcount[(size_t)r],
+    launch_phase(p, slot, ritem_per_thread[(size_t)r], slot->dev + rstart[(size_t)r], (int)rcount[(size_t)r],
                  rtiles[(size_t)r], record);
     if (record)
-      hipLaunchKernelGGL(k_compress_hooked, dim3(1024), dim3(256), 0, p->stream, p->arena, p->hooked, p->ctl,
-                         (int32_t)std::min<int64_t>(p->capacity, 0x7fffffff), p->flags);
+      hipLaunchKernelGGL(k_compress_hooked, dim3(1024), dim3(256), 0, p->stream, p->arena, slot->hooked,
+                         slot->ctl, (int32_t)std::min<int64_t>(p->capacity, 0x7fffffff), p->flags);
   }
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipEventRecord(slot->done, p->stream));

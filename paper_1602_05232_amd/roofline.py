@@ -69,3 +69,27 @@ def copy_bytes(dst: torch.Tensor, src: torch.Tensor, nbytes: int):
 def edge_roofline(G: float, Bs: float) -> float:
     """Bulk-Update edges/s bound: 2 random parent reads + 8 streamed bytes per edge."""
     return 1.0 / (2.0 / G + 8.0 / Bs)
+
+
+def _main():
+    """Command line: `python -m paper_1602_05232_amd.roofline copy [bytes]` runs
+    one plain copy kernel of known size (the reference point for traffic
+    counters); `... gather [log2 table]` prints G for one table size."""
+    import sys
+    what = sys.argv[1] if len(sys.argv) > 1 else "gather"
+    if what == "copy":
+        nbytes = int(sys.argv[2]) if len(sys.argv) > 2 else 1 << 30
+        src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        copy_bytes(dst, src, nbytes)
+        torch.cuda.synchronize()
+        assert torch.equal(src, dst)
+        print("copied %d bytes with one ccb_copy launch" % nbytes, flush=True)
+    else:
+        lg = int(sys.argv[2]) if len(sys.argv) > 2 else 24
+        print("G(2^%d) = %.4g gathers/s" % (lg, gather_rate(1 << lg)), flush=True)
+
+
+if __name__ == "__main__":
+    _main()

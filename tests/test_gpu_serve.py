@@ -1,0 +1,56 @@
+"""The serving loop on the GPU pool: every query answer equals the oracle's
+for its stream, alone and in the mix, with and without evictions."""
+import numpy as np
+import pytest
+import torch
+
+from test_serve import expected_answers, make_trace
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def serve():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1602_05232_amd.serve as serve
+    import paper_1602_05232_amd as ccgpu
+    ccgpu.lib()
+    return serve
+
+
+def to_gpu(serve, reqs):
+    out = []
+    for r in reqs:
+        items = torch.from_numpy(np.ascontiguousarray(r.items)).cuda()
+        o = torch.zeros(r.size, dtype=torch.uint8, device="cuda") if r.kind == serve.QUERY else None
+        out.append(serve.Request(r.rid, r.stream, r.kind, r.arrival, items, o, r.size))
+    torch.cuda.synchronize()
+    return out
+
+
+@pytest.mark.parametrize("budget_graphs", [None, 3])
+def test_gpu_serving_matches_oracle(serve, budget_graphs):
+    ns, reqs = make_trace(S=12, R=300, rate=5e4, seed=21, nmax=1 << 12)
+    want, _ = expected_answers(ns, reqs)
+    budget = sum(ns) if budget_graphs is None else max(ns) * budget_graphs
+    ex = serve.GpuExecutor(budget, len(ns) + 1)
+    sch = serve.Scheduler(ex, ns, max_inflight=2)
+    done = sch.run(to_gpu(serve, reqs))
+    torch.cuda.synchronize()
+    for r in done:
+        if r.kind == serve.QUERY:
+            np.testing.assert_array_equal(r.out.cpu().numpy(), want[r.rid], err_msg="request %d" % r.rid)
+    if budget_graphs is not None:
+        assert sch.evictions > 0
+    assert ex.pool.sync() == 0
+    ex.close()
+    # one stream alone
+    s0 = [r for r in reqs if r.stream == 0]
+    ex = serve.GpuExecutor(ns[0], 2)
+    done = serve.Scheduler(ex, ns, max_inflight=2).run(to_gpu(serve, s0))
+    torch.cuda.synchronize()
+    for r in done:
+        if r.kind == serve.QUERY:
+            np.testing.assert_array_equal(r.out.cpu().numpy(), want[r.rid])
+    ex.close()
