@@ -77,7 +77,12 @@ enum cc_option {
    * point every vertex on their paths straight at the root (the "pragmatic"
    * path compression of Section 6.1, limited to what the minibatch changed);
    * 0 = rely on path halving alone.  Default 1. */
-  CC_OPT_COMPRESS_LINKED = 8
+  CC_OPT_COMPRESS_LINKED = 8,
+  /* cc_bulk_stream: how many sleeps (about 60 ns each) a block waits at a
+   * device-wide barrier before it gives up, raises the timeout condition
+   * (reported by cc_sync as CC_EDEVICE) and makes every block leave the
+   * kernel.  Default 2^24 (about one second). */
+  CC_OPT_SPIN_LIMIT = 9
 };
 
 /* Create a graph on vertices [0, n), 1 <= n <= 2^31 - 1, every vertex its own
@@ -121,6 +126,21 @@ int cc_bulk_update(cc_graph* g, const int32_t* edges, int64_t m);
  * device int32[q][2], out is device uint8[q], written in input order.  A pair
  * (u, u) answers 1. */
 int cc_bulk_query(cc_graph* g, const int32_t* pairs, int64_t q, uint8_t* out);
+
+/* A whole stream in one launch: for k = 0 .. batches-1, Bulk-Update of edges
+ * [eoff[k], eoff[k+1]) and then Bulk-Query of pairs [qoff[k], qoff[k+1]) with
+ * answers out[qoff[k] ..], exactly as the same sequence of cc_bulk_update and
+ * cc_bulk_query calls (each bulk operation completes before the next begins,
+ * Section 1).  edges and pairs are device int32[][2]; eoff and qoff are
+ * DEVICE int64[batches+1] item offsets into them; out is device uint8 indexed
+ * like pairs.  max_items (>= 1) bounds the items of any one operation and
+ * sizes the grid.  The operations are separated by device-wide barriers
+ * inside one cooperative launch, for streams of many small minibatches whose
+ * separate launches would cost mostly launch latency.  Not available during
+ * capture.  A barrier that waits past CC_OPT_SPIN_LIMIT ends the kernel and
+ * is reported by cc_sync as CC_EDEVICE. */
+int cc_bulk_stream(cc_graph* g, int64_t batches, const int32_t* edges, const int64_t* eoff,
+                   const int32_t* pairs, const int64_t* qoff, uint8_t* out, int64_t max_items);
 
 /* Canonical component labels: out[v] = the smallest vertex id connected to v
  * (the paper's find returns "an identifier" of the component, Section 4;

@@ -39,7 +39,7 @@ def _median_pass(fn, reps):
 
 def plain_candidates(quick=False):
     out = []
-    for block, items, cl, hook in itertools.product((256, 512, 1024), (0, 4, 8), (0, 1), (0, 1)):
+    for block, items, cl, hook in itertools.product((256, 512, 1024), (0, 4, 8), (0, 1), (0, 1, 2)):
         out.append(dict(update_mode=0, block=block, items=items, compress_linked=cl, hook=hook))
     out += [dict(update_mode=1, block=b, items=0) for b in (256, 1024)]
     if quick:

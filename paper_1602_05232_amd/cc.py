@@ -17,10 +17,11 @@ LIB_PATH = os.path.join(_HERE, "libcc.so")
 
 CC_OK, CC_EINVAL, CC_ENOMEM, CC_ERANGE, CC_EDEVICE, CC_ECORRUPT = 0, -1, -2, -3, -4, -5
 OPT_UPDATE_MODE, OPT_BLOCK, OPT_ITEMS, OPT_QUERY_HALVING = 1, 2, 3, 4
-OPT_COMPRESS_EVERY, OPT_HOOK, OPT_GRID_CAP, OPT_COMPRESS_LINKED = 5, 6, 7, 8
+OPT_COMPRESS_EVERY, OPT_HOOK, OPT_GRID_CAP, OPT_COMPRESS_LINKED, OPT_SPIN_LIMIT = 5, 6, 7, 8, 9
 _OPT_NAMES = {"update_mode": OPT_UPDATE_MODE, "block": OPT_BLOCK, "items": OPT_ITEMS,
               "query_halving": OPT_QUERY_HALVING, "compress_every": OPT_COMPRESS_EVERY,
-              "hook": OPT_HOOK, "grid_cap": OPT_GRID_CAP, "compress_linked": OPT_COMPRESS_LINKED}
+              "hook": OPT_HOOK, "grid_cap": OPT_GRID_CAP, "compress_linked": OPT_COMPRESS_LINKED,
+              "spin_limit": OPT_SPIN_LIMIT}
 
 # Every symbol include/cc.h declares, with (restype, argtypes).
 _vp, _i64, _i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
@@ -34,6 +35,7 @@ SIGNATURES = {
     "cc_reset": (_i32, [_vp]),
     "cc_bulk_update": (_i32, [_vp, _vp, _i64]),
     "cc_bulk_query": (_i32, [_vp, _vp, _i64, _vp]),
+    "cc_bulk_stream": (_i32, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _i64]),
     "cc_labels": (_i32, [_vp, _vp]),
     "cc_num_components": (_i32, [_vp, ctypes.POINTER(_i64)]),
     "cc_count_roots": (_i32, [_vp, ctypes.POINTER(_i64)]),
@@ -205,6 +207,20 @@ class Graph:
         assert out.dtype == torch.uint8 and out.is_cuda and out.numel() >= q and out.is_contiguous()
         _check(lib().cc_bulk_query(self._h, p, q, out.data_ptr()))
         return out
+
+    def bulk_stream(self, edges: torch.Tensor, eoff: torch.Tensor, pairs: torch.Tensor, qoff: torch.Tensor,
+                    out: torch.Tensor, max_items: int | None = None):
+        """Every (update k, query k) of a stream in one launch; eoff/qoff are
+        CUDA int64 offsets (length batches + 1) into edges/pairs."""
+        for t, name in ((eoff, "eoff"), (qoff, "qoff")):
+            if not (t.is_cuda and t.dtype == torch.int64 and t.dim() == 1 and t.is_contiguous()):
+                raise TypeError("%s must be a contiguous CUDA int64 vector" % name)
+        batches = eoff.numel() - 1
+        assert qoff.numel() == batches + 1 and out.dtype == torch.uint8 and out.is_cuda
+        if max_items is None:
+            max_items = int(max(torch.diff(eoff).max().item(), torch.diff(qoff).max().item(), 1))
+        _check(lib().cc_bulk_stream(self._h, batches, _pairs_ptr(edges, "edges"), eoff.data_ptr(),
+                                    _pairs_ptr(pairs, "pairs"), qoff.data_ptr(), out.data_ptr(), int(max_items)))
 
     def labels(self, out: torch.Tensor | None = None) -> torch.Tensor:
         if out is None:

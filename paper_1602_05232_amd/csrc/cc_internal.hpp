@@ -5,6 +5,8 @@
 #include <stdarg.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "../../include/cc.h"
 
 void cc_set_error(const char* fmt, ...);
@@ -49,6 +51,7 @@ struct Tuning {
   int hook = 0;             // CC_OPT_HOOK
   int grid_cap = 4096;      // CC_OPT_GRID_CAP
   int compress_linked = 1;  // CC_OPT_COMPRESS_LINKED
+  int64_t spin_limit = 1 << 24;  // CC_OPT_SPIN_LIMIT
 };
 
 inline bool set_tuning(Tuning* t, int key, int64_t v) {
@@ -74,7 +77,7 @@ inline bool set_tuning(Tuning* t, int key, int64_t v) {
       t->compress_every = v;
       return true;
     case CC_OPT_HOOK:
-      if (v != 0 && v != 1) return false;
+      if (v < 0 || v > 2) return false;
       t->hook = (int)v;
       return true;
     case CC_OPT_GRID_CAP:
@@ -84,6 +87,10 @@ inline bool set_tuning(Tuning* t, int key, int64_t v) {
     case CC_OPT_COMPRESS_LINKED:
       if (v != 0 && v != 1) return false;
       t->compress_linked = (int)v;
+      return true;
+    case CC_OPT_SPIN_LIMIT:
+      if (v < 0 || v > 0xffffffffLL) return false;
+      t->spin_limit = v;
       return true;
     default:
       return false;
@@ -100,6 +107,7 @@ inline bool get_tuning(const Tuning* t, int key, int64_t* v) {
     case CC_OPT_HOOK: *v = t->hook; return true;
     case CC_OPT_GRID_CAP: *v = t->grid_cap; return true;
     case CC_OPT_COMPRESS_LINKED: *v = t->compress_linked; return true;
+    case CC_OPT_SPIN_LIMIT: *v = t->spin_limit; return true;
     default: return false;
   }
 }
@@ -124,8 +132,40 @@ inline uint32_t fmix32_host(uint32_t h) {
 
 // A parent image is a valid forest under the linking order when every
 // pointer stays in range and goes from lower to strictly higher priority
-// (then no cycle is possible).  Counts the roots.
+// (then no cycle is possible).  Under union by rank (hook 2) a root's word
+// carries its rank in the bits above kRankShift and the order is not
+// recoverable from the image, so every path is walked instead (each node is
+// visited once; a walk that meets itself is a cycle).  Counts the roots.
 inline bool check_forest(const int32_t* p, int64_t n, int hook, int64_t* roots) {
+  if (hook == 2) {
+    constexpr int32_t mask = (1 << 27) - 1;
+    std::vector<uint8_t> state((size_t)n, 0);  // 0 new, 1 on the current walk, 2 done
+    int64_t r = 0;
+    for (int64_t v = 0; v < n; ++v) {
+      int64_t x = v;
+      while (state[(size_t)x] == 0) {
+        state[(size_t)x] = 1;
+        const int32_t w = p[x];  // a high rank sets the sign bit
+        const int32_t q = w & mask;
+        if (q >= n) return false;
+        if (q == x) {
+          ++r;
+          break;
+        }
+        if (w != q) return false;  // only roots carry rank bits
+        x = q;
+      }
+      if (state[(size_t)x] == 1 && (p[x] & mask) != x) return false;  // met its own walk
+      for (int64_t y = v; state[(size_t)y] == 1;) {
+        state[(size_t)y] = 2;
+        const int32_t q = p[y] & mask;
+        if (q == y) break;
+        y = q;
+      }
+    }
+    *roots = r;
+    return true;
+  }
   int64_t r = 0;
   for (int64_t v = 0; v < n; ++v) {
     const int32_t q = p[v];

@@ -80,6 +80,7 @@ template <int ITEMS, class Ord, bool RECORD>
 __global__ void k_update_fused(int32_t* __restrict__ parent, const int2* __restrict__ edges, int64_t m,
                                int32_t n, unsigned long long* __restrict__ slots, int* __restrict__ flags,
                                int32_t* __restrict__ hooked, unsigned* __restrict__ hooked_ctl) {
+  constexpr bool R = is_ranked<Ord>::value;
   __shared__ int wave_off[16];
   __shared__ unsigned blk[2];
   const int64_t tile = (int64_t)blockDim.x * ITEMS;
@@ -102,12 +103,12 @@ __global__ void k_update_fused(int32_t* __restrict__ parent, const int2* __restr
       }
       const int32_t u = e[k].x, v = e[k].y;
       if (u == v) continue;
-      const int32_t pu = ld(parent + u), pv = ld(parent + v);
+      const int32_t pu = ldp<R>(parent + u), pv = ldp<R>(parent + v);
       if (pu == pv || pu == v || pv == u) continue;  // already one tree
-      const int32_t ru = find_halve_from(parent, u, pu, n, flags);
-      const int32_t rv = find_halve_from(parent, v, pv, n, flags);
+      const int32_t ru = find_halve_from<R>(parent, u, pu, n, flags);
+      const int32_t rv = find_halve_from<R>(parent, v, pv, n, flags);
       if (ru != rv) {
-        hk[k] = link_roots(parent, ru, rv, n, flags, Ord{});
+        hk[k] = link(parent, ru, rv, n, flags, Ord{});
         if (hk[k] >= 0) ++nh;
       }
     }
@@ -195,14 +196,15 @@ __global__ void k_link_live(int32_t* __restrict__ parent, const int2* __restrict
 
 // Full compression of x's path: find the root, then re-walk and point each
 // node at it.  Only valid while nothing is being linked.
+template <bool R = false>
 __device__ __forceinline__ void compress_path(int32_t* parent, int32_t x, int32_t n, int* flags) {
-  const int32_t r = find_read(parent, x, n, flags);
+  const int32_t r = find_read<R>(parent, x, n, flags);
   int32_t steps = 0;
-  int32_t p = ld(parent + x);
+  int32_t p = ldp<R>(parent + x);
   while (p != r && p != x) {
     st(parent + x, r);
     x = p;
-    p = ld(parent + x);
+    p = ldp<R>(parent + x);
     if (++steps > n) break;
   }
 }
@@ -232,11 +234,12 @@ __global__ void k_compress_live(int32_t* __restrict__ parent, const int2* __rest
 // Compress the paths of the roots linked by the last fused update (the
 // "pragmatic" compression of Section 6.1 applied to the nodes the minibatch
 // changed), then the last block clears the list's count.
+template <bool R = false>
 __global__ void k_compress_hooked(int32_t* __restrict__ parent, const int32_t* __restrict__ hooked,
                                   unsigned* __restrict__ ctl, int32_t n, int* __restrict__ flags) {
   const unsigned L = __hip_atomic_load(ctl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < L; i += gridDim.x * blockDim.x)
-    compress_path(parent, hooked[i], n, flags);
+    compress_path<R>(parent, hooked[i], n, flags);
   __syncthreads();
   if (threadIdx.x == 0) {
     const unsigned done = __hip_atomic_fetch_add(ctl + 1, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
@@ -247,7 +250,7 @@ __global__ void k_compress_hooked(int32_t* __restrict__ parent, const int32_t* _
   }
 }
 
-template <int ITEMS, bool HALVE>
+template <int ITEMS, bool HALVE, bool R = false>
 __global__ void k_query(int32_t* __restrict__ parent, const int2* __restrict__ pairs, int64_t q, int32_t n,
                         uint8_t* __restrict__ out, int* __restrict__ flags) {
   const int64_t tile = (int64_t)blockDim.x * ITEMS;
@@ -267,8 +270,8 @@ __global__ void k_query(int32_t* __restrict__ parent, const int2* __restrict__ p
       } else if (e[k].x == e[k].y) {
         a = 1;
       } else {
-        const int32_t ru = find_root<HALVE>(parent, e[k].x, n, flags);
-        const int32_t rv = find_root<HALVE>(parent, e[k].y, n, flags);
+        const int32_t ru = find_root<HALVE, R>(parent, e[k].x, n, flags);
+        const int32_t rv = find_root<HALVE, R>(parent, e[k].y, n, flags);
         a = ru == rv;
       }
       if (i < q) out[i] = a;
@@ -293,38 +296,42 @@ __global__ void k_fill_i32(int32_t* __restrict__ out, int32_t n, int32_t value) 
 
 // Hashed order, pass 1: the minimum id of each tree collects in its root's slot
 // (out pre-filled with n).
+template <bool R = false>
 __global__ void k_labels_min(int32_t* __restrict__ parent, int32_t n, int32_t* __restrict__ out,
                              int* __restrict__ flags) {
   for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
-    const int32_t r = find_halve(parent, v, n, flags);
-    if (ld(parent + v) != r) st(parent + v, r);
+    const int32_t r = find_halve<R>(parent, v, n, flags);
+    if (r != v && ld(parent + v) != r) st(parent + v, r);
     atomicMin(out + r, v);
   }
 }
 
 // Hashed order, pass 2: every vertex copies its root's minimum.  A root
 // rewrites its own slot with the same value; non-root slots are never read.
+template <bool R = false>
 __global__ void k_labels_gather(const int32_t* __restrict__ parent, int32_t n, int32_t* __restrict__ out,
                                 int* __restrict__ flags) {
   for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
-    const int32_t r = find_read(parent, v, n, flags);
+    const int32_t r = find_read<R>(parent, v, n, flags);
     out[v] = out[r];
   }
 }
 
+template <bool R = false>
 __global__ void k_compress_all(int32_t* __restrict__ parent, int32_t n, int* __restrict__ flags) {
   for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
-    const int32_t r = find_halve(parent, v, n, flags);
-    if (ld(parent + v) != r) st(parent + v, r);
+    const int32_t r = find_halve<R>(parent, v, n, flags);
+    if (r != v && ld(parent + v) != r) st(parent + v, r);
   }
 }
 
+template <bool R = false>
 __global__ void k_count_roots(const int32_t* __restrict__ parent, int32_t n,
                               unsigned long long* __restrict__ result) {
   __shared__ int part[16];
   int c = 0;
   for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
-    c += parent[v] == v;
+    c += pid<R>(parent[v]) == v;
   c = wave_sum(c);
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
   __syncthreads();

@@ -10,8 +10,9 @@
 #include <vector>
 
 #include "../../include/cc.h"
-#include "cc_kernels.hpp"
 #include "cc_internal.hpp"
+#include "cc_kernels.hpp"
+#include "cc_stream_kernels.hpp"
 
 using namespace ccdev;
 using cc::blocks_for;
@@ -125,8 +126,8 @@ void launch_fused_o(cc_graph* g, const int2* e, int64_t m) {
   if (g->tune.compress_linked) {
     launch_fused_r<Ord, true>(g, e, m);
     const unsigned blocks = blocks_for(std::min<int64_t>(m, g->n), 256, 1024);
-    hipLaunchKernelGGL(k_compress_hooked, dim3(blocks), dim3(256), 0, g->stream, g->parent, g->hooked,
-                       g->live_ctl + 2, (int32_t)g->n, g->flags);
+    hipLaunchKernelGGL(k_compress_hooked<is_ranked<Ord>::value>, dim3(blocks), dim3(256), 0, g->stream,
+                       g->parent, g->hooked, g->live_ctl + 2, (int32_t)g->n, g->flags);
   } else {
     launch_fused_r<Ord, false>(g, e, m);
   }
@@ -156,21 +157,21 @@ void launch_split_o(cc_graph* g, const int2* e, int64_t m) {
                      (int32_t)g->n, g->flags);
 }
 
-template <int ITEMS, bool HALVE>
+template <int ITEMS, bool HALVE, bool R>
 void launch_query_t(cc_graph* g, const int2* p, int64_t q, uint8_t* out) {
   const int B = g->tune.block;
   const unsigned blocks = blocks_for(q, (int64_t)B * ITEMS, g->tune.grid_cap);
-  hipLaunchKernelGGL((k_query<ITEMS, HALVE>), dim3(blocks), dim3(B), 0, g->stream, g->parent, p, q,
+  hipLaunchKernelGGL((k_query<ITEMS, HALVE, R>), dim3(blocks), dim3(B), 0, g->stream, g->parent, p, q,
                      (int32_t)g->n, out, g->flags);
 }
 
-template <bool HALVE>
+template <bool HALVE, bool R>
 void launch_query_h(cc_graph* g, const int2* p, int64_t q, uint8_t* out) {
   switch (cc::pick_items(g->tune.items, q, g->tune.block)) {
-    case 1: launch_query_t<1, HALVE>(g, p, q, out); break;
-    case 2: launch_query_t<2, HALVE>(g, p, q, out); break;
-    case 8: launch_query_t<8, HALVE>(g, p, q, out); break;
-    default: launch_query_t<4, HALVE>(g, p, q, out); break;
+    case 1: launch_query_t<1, HALVE, R>(g, p, q, out); break;
+    case 2: launch_query_t<2, HALVE, R>(g, p, q, out); break;
+    case 8: launch_query_t<8, HALVE, R>(g, p, q, out); break;
+    default: launch_query_t<4, HALVE, R>(g, p, q, out); break;
   }
 }
 
@@ -252,6 +253,10 @@ extern "C" int cc_set_stream(cc_graph* g, void* stream) {
 
 extern "C" int cc_set_option(cc_graph* g, int key, int64_t value) {
   if (!g) return CC_EINVAL;
+  if (key == CC_OPT_HOOK && value == 2 && g->n > (int64_t)kIdMask + 1) {
+    cc_set_error("cc_set_option: union by rank needs n <= 2^%d", kRankShift);
+    return CC_EINVAL;
+  }
   if (!cc::set_tuning(&g->tune, key, value)) {
     cc_set_error("cc_set_option: key %d value %lld rejected", key, (long long)value);
     return CC_EINVAL;
@@ -292,7 +297,11 @@ extern "C" int cc_bulk_update(cc_graph* g, const int32_t* edges, int64_t m) {
   if (m == 0) return CC_OK;
   DeviceGuard dg(g->device);
   const int2* e = reinterpret_cast<const int2*>(edges);
-  const bool hashed = g->tune.hook == 1;
+  const bool hashed = g->tune.hook == 1, ranked = g->tune.hook == 2;
+  if (ranked && g->tune.mode == 1) {
+    cc_set_error("cc_bulk_update: union by rank runs with the fused schedule only");
+    return CC_EINVAL;
+  }
   if (g->tune.mode == 1) {
     if (g->capturing && m > g->live_cap) {
       cc_set_error("cc_bulk_update: split update of %lld edges exceeds the reserved %lld during capture",
@@ -312,13 +321,19 @@ extern "C" int cc_bulk_update(cc_graph* g, const int32_t* edges, int64_t m) {
       int rc = alloc_hooked(g);
       if (rc != CC_OK) return rc;
     }
-    if (hashed) launch_fused_o<ByHash>(g, e, m);
+    if (ranked) launch_fused_o<ByRank>(g, e, m);
+    else if (hashed) launch_fused_o<ByHash>(g, e, m);
     else launch_fused_o<ById>(g, e, m);
   }
   g->updates++;
-  if (g->tune.compress_every > 0 && g->updates % g->tune.compress_every == 0)
-    hipLaunchKernelGGL(k_compress_all, dim3(vertex_blocks(g)), dim3(256), 0, g->stream, g->parent,
-                       (int32_t)g->n, g->flags);
+  if (g->tune.compress_every > 0 && g->updates % g->tune.compress_every == 0) {
+    if (ranked)
+      hipLaunchKernelGGL(k_compress_all<true>, dim3(vertex_blocks(g)), dim3(256), 0, g->stream, g->parent,
+                         (int32_t)g->n, g->flags);
+    else
+      hipLaunchKernelGGL(k_compress_all<false>, dim3(vertex_blocks(g)), dim3(256), 0, g->stream, g->parent,
+                         (int32_t)g->n, g->flags);
+  }
   HIP_TRY(hipGetLastError());
   return CC_OK;
 }
@@ -331,8 +346,14 @@ extern "C" int cc_bulk_query(cc_graph* g, const int32_t* pairs, int64_t q, uint8
   if (q == 0) return CC_OK;
   DeviceGuard dg(g->device);
   const int2* p = reinterpret_cast<const int2*>(pairs);
-  if (g->tune.query_halving) launch_query_h<true>(g, p, q, out);
-  else launch_query_h<false>(g, p, q, out);
+  const bool ranked = g->tune.hook == 2;
+  if (g->tune.query_halving) {
+    if (ranked) launch_query_h<true, true>(g, p, q, out);
+    else launch_query_h<true, false>(g, p, q, out);
+  } else {
+    if (ranked) launch_query_h<false, true>(g, p, q, out);
+    else launch_query_h<false, false>(g, p, q, out);
+  }
   HIP_TRY(hipGetLastError());
   return CC_OK;
 }
@@ -344,8 +365,14 @@ extern "C" int cc_labels(cc_graph* g, int32_t* out) {
   const int32_t n = (int32_t)g->n;
   if (g->tune.hook == 1) {
     hipLaunchKernelGGL(k_fill_i32, dim3(blocks), dim3(256), 0, g->stream, out, n, n);
-    hipLaunchKernelGGL(k_labels_min, dim3(blocks), dim3(256), 0, g->stream, g->parent, n, out, g->flags);
-    hipLaunchKernelGGL(k_labels_gather, dim3(blocks), dim3(256), 0, g->stream, g->parent, n, out, g->flags);
+    hipLaunchKernelGGL(k_labels_min<false>, dim3(blocks), dim3(256), 0, g->stream, g->parent, n, out, g->flags);
+    hipLaunchKernelGGL(k_labels_gather<false>, dim3(blocks), dim3(256), 0, g->stream, g->parent, n, out,
+                       g->flags);
+  } else if (g->tune.hook == 2) {
+    hipLaunchKernelGGL(k_fill_i32, dim3(blocks), dim3(256), 0, g->stream, out, n, n);
+    hipLaunchKernelGGL(k_labels_min<true>, dim3(blocks), dim3(256), 0, g->stream, g->parent, n, out, g->flags);
+    hipLaunchKernelGGL(k_labels_gather<true>, dim3(blocks), dim3(256), 0, g->stream, g->parent, n, out,
+                       g->flags);
   } else {
     hipLaunchKernelGGL(k_labels_id, dim3(blocks), dim3(256), 0, g->stream, g->parent, n, out, g->flags);
   }
@@ -375,8 +402,12 @@ extern "C" int cc_count_roots(cc_graph* g, int64_t* out) {
   }
   DeviceGuard dg(g->device);
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, g->stream, g->red, 1);
-  hipLaunchKernelGGL(k_count_roots, dim3(vertex_blocks(g)), dim3(256), 0, g->stream, g->parent,
-                     (int32_t)g->n, g->red);
+  if (g->tune.hook == 2)
+    hipLaunchKernelGGL(k_count_roots<true>, dim3(vertex_blocks(g)), dim3(256), 0, g->stream, g->parent,
+                       (int32_t)g->n, g->red);
+  else
+    hipLaunchKernelGGL(k_count_roots<false>, dim3(vertex_blocks(g)), dim3(256), 0, g->stream, g->parent,
+                       (int32_t)g->n, g->red);
   HIP_TRY(hipGetLastError());
   unsigned long long h = 0;
   HIP_TRY(hipMemcpyAsync(&h, g->red, 8, hipMemcpyDeviceToHost, g->stream));
@@ -399,6 +430,10 @@ extern "C" int cc_sync(cc_graph* g) {
   if (f) {
     HIP_TRY(hipMemsetAsync(g->flags, 0, sizeof(int), g->stream));
     HIP_TRY(hipStreamSynchronize(g->stream));
+  }
+  if (f & kFlagTimeout) {
+    cc_set_error("a device-wide barrier of cc_bulk_stream timed out; its results are incomplete");
+    return CC_EDEVICE;
   }
   if (f & kFlagCorrupt) {
     cc_set_error("a find exceeded n steps: the forest holds a cycle");
@@ -511,4 +546,52 @@ extern "C" int cc_exec_destroy(cc_exec* x) {
   (void)hipGraphExecDestroy(x->exec);
   delete x;
   return CC_OK;
+}
+
+namespace {
+
+template <class Ord>
+int launch_stream(cc_graph* g, int64_t batches, const int32_t* edges, const int64_t* eoff, const int32_t* pairs,
+                  const int64_t* qoff, uint8_t* out, int64_t max_items) {
+  const int block = 256;
+  int per_cu = 0, cus = 0;
+  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_stream<Ord>, block, 0));
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device));
+  int64_t grid = (max_items + block - 1) / block;
+  grid = std::min<int64_t>(grid, (int64_t)per_cu * cus);
+  grid = std::min<int64_t>(grid, 1024);
+  grid = std::max<int64_t>(grid, 1);
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, g->stream, g->live_ctl + 4, 3);
+  HIP_TRY(hipGetLastError());
+  int32_t* parent = g->parent;
+  const int2* e = reinterpret_cast<const int2*>(edges);
+  const int2* p = reinterpret_cast<const int2*>(pairs);
+  int32_t n = (int32_t)g->n;
+  unsigned long long* slots = g->slots;
+  int* flags = g->flags;
+  unsigned* bar = g->live_ctl + 4;
+  unsigned spin = (unsigned)g->tune.spin_limit;
+  void* args[] = {&parent, &batches, &e, &eoff, &p, &qoff, &out, &n, &slots, &flags, &bar, &spin};
+  HIP_TRY(hipLaunchCooperativeKernel((const void*)k_stream<Ord>, dim3((unsigned)grid), dim3(block), args, 0,
+                                     g->stream));
+  return CC_OK;
+}
+
+}  // namespace
+
+extern "C" int cc_bulk_stream(cc_graph* g, int64_t batches, const int32_t* edges, const int64_t* eoff,
+                              const int32_t* pairs, const int64_t* qoff, uint8_t* out, int64_t max_items) {
+  if (!g || batches < 0 || max_items < 1 || (batches > 0 && (!edges || !eoff || !pairs || !qoff || !out))) {
+    cc_set_error("cc_bulk_stream: invalid argument");
+    return CC_EINVAL;
+  }
+  if (g->capturing) {
+    cc_set_error("cc_bulk_stream: not available while capturing");
+    return CC_EINVAL;
+  }
+  if (batches == 0) return CC_OK;
+  DeviceGuard dg(g->device);
+  if (g->tune.hook == 1) return launch_stream<ByHash>(g, batches, edges, eoff, pairs, qoff, out, max_items);
+  if (g->tune.hook == 2) return launch_stream<ByRank>(g, batches, edges, eoff, pairs, qoff, out, max_items);
+  return launch_stream<ById>(g, batches, edges, eoff, pairs, qoff, out, max_items);
 }

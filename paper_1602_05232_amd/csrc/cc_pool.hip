@@ -222,6 +222,10 @@ extern "C" int cc_pool_set_option(cc_pool* p, int key, int64_t value) {
     cc_set_error("cc_pool_set_option: option %d does not apply to pools", key);
     return CC_EINVAL;
   }
+  if (key == CC_OPT_HOOK && value == 2) {
+    cc_set_error("cc_pool_set_option: union by rank is not available in pools");
+    return CC_EINVAL;
+  }
   if (key == CC_OPT_HOOK) {
     for (const auto& g : p->graphs)
       if (g.used) {

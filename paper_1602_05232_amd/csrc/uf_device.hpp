@@ -36,6 +36,7 @@ namespace ccdev {
 
 constexpr int kFlagRange = 1;
 constexpr int kFlagCorrupt = 2;
+constexpr int kFlagTimeout = 4;
 constexpr int kSlots = 64;       // union counters, spread to cut atomic contention
 constexpr int kSlotStride = 16;  // 16 x u64 = 128 B between counters
 
@@ -79,16 +80,32 @@ struct ByHash {
   }
 };
 
-// Root of x with path halving, given p = parent[x] already loaded.
+// Union by rank keeps each root's rank in the top bits of the root's own
+// word (ids need at most kRankShift bits); a non-root word is a plain id.
+// Finds under that layout mask the rank bits off (template flag R).
+constexpr int kRankShift = 27;
+constexpr int32_t kIdMask = (1 << kRankShift) - 1;
+
+template <bool R>
+__device__ __forceinline__ int32_t pid(int32_t w) {
+  return R ? (w & kIdMask) : w;
+}
+template <bool R>
+__device__ __forceinline__ int32_t ldp(const int32_t* p) {
+  return pid<R>(ld(p));
+}
+
+// Root of x with path halving, given p = parent id of x already loaded.
+template <bool R = false>
 __device__ __forceinline__ int32_t find_halve_from(int32_t* parent, int32_t x, int32_t p, int32_t cap,
                                                    int* flags) {
   int32_t steps = 0;
   while (p != x) {
-    int32_t g = ld(parent + p);
+    int32_t g = ldp<R>(parent + p);
     if (g == p) return p;
     st(parent + x, g);
     x = g;
-    p = ld(parent + x);
+    p = ldp<R>(parent + x);
     if (++steps > cap) {
       raise_flag(flags, kFlagCorrupt);
       return x;
@@ -98,17 +115,19 @@ __device__ __forceinline__ int32_t find_halve_from(int32_t* parent, int32_t x, i
 }
 
 // Root of x with path halving.
+template <bool R = false>
 __device__ __forceinline__ int32_t find_halve(int32_t* parent, int32_t x, int32_t cap, int* flags) {
-  return find_halve_from(parent, x, ld(parent + x), cap, flags);
+  return find_halve_from<R>(parent, x, ldp<R>(parent + x), cap, flags);
 }
 
 // Root of x without writing.
+template <bool R = false>
 __device__ __forceinline__ int32_t find_read(const int32_t* parent, int32_t x, int32_t cap, int* flags) {
-  int32_t p = ld(parent + x);
+  int32_t p = ldp<R>(parent + x);
   int32_t steps = 0;
   while (p != x) {
     x = p;
-    p = ld(parent + x);
+    p = ldp<R>(parent + x);
     if (++steps > cap) {
       raise_flag(flags, kFlagCorrupt);
       return x;
@@ -117,10 +136,10 @@ __device__ __forceinline__ int32_t find_read(const int32_t* parent, int32_t x, i
   return x;
 }
 
-template <bool HALVE>
+template <bool HALVE, bool R = false>
 __device__ __forceinline__ int32_t find_root(int32_t* parent, int32_t x, int32_t cap, int* flags) {
-  if (HALVE) return find_halve(parent, x, cap, flags);
-  return find_read(parent, x, cap, flags);
+  if (HALVE) return find_halve<R>(parent, x, cap, flags);
+  return find_read<R>(parent, x, cap, flags);
 }
 
 // Join the trees whose (possibly stale) roots are a and b.  Returns the vertex
@@ -145,6 +164,60 @@ __device__ __forceinline__ int32_t link_roots(int32_t* parent, int32_t a, int32_
     }
   }
   return -1;
+}
+
+// Union by rank (the balanced linking of the Section 4 union-find, with
+// ranks in place of sizes): the root of lower (rank, id) is linked under the
+// other; on equal ranks the winner's rank then grows by one.  The CAS checks
+// the loser's whole word (still a root, same rank), and a root's (rank, id)
+// only grows, so keys strictly increase along every parent path: no cycle.
+// A rank increment that loses a race is skipped; ranks only steer balance.
+__device__ __forceinline__ int32_t link_roots_rank(int32_t* parent, int32_t a, int32_t b, int32_t cap,
+                                                   int* flags) {
+  int32_t steps = 0;
+  while (a != b) {
+    const int32_t wa = ld(parent + a), wb = ld(parent + b);
+    if ((wa & kIdMask) != a) {
+      a = find_halve_from<true>(parent, a, wa & kIdMask, cap, flags);
+    } else if ((wb & kIdMask) != b) {
+      b = find_halve_from<true>(parent, b, wb & kIdMask, cap, flags);
+    } else {
+      const int32_t ra = (int32_t)((uint32_t)wa >> kRankShift), rb = (int32_t)((uint32_t)wb >> kRankShift);
+      const bool a_loses = ra < rb || (ra == rb && a > b);
+      const int32_t lo = a_loses ? a : b, hi = a_loses ? b : a;
+      const int32_t wl = a_loses ? wa : wb, ww = a_loses ? wb : wa;
+      if (cas(parent + lo, wl, hi) == wl) {
+        if (ra == rb) (void)cas(parent + hi, ww, (int32_t)((uint32_t)ww + (1u << kRankShift)));
+        return lo;
+      }
+    }
+    if (++steps > cap) {
+      raise_flag(flags, kFlagCorrupt);
+      return -1;
+    }
+  }
+  return -1;
+}
+
+// Marker of the rank order, and the link call for each order.
+struct ByRank {};
+template <class Ord>
+struct is_ranked {
+  static constexpr bool value = false;
+};
+template <>
+struct is_ranked<ByRank> {
+  static constexpr bool value = true;
+};
+
+template <class Ord>
+__device__ __forceinline__ int32_t link(int32_t* parent, int32_t a, int32_t b, int32_t cap, int* flags,
+                                        const Ord& o) {
+  return link_roots(parent, a, b, cap, flags, o);
+}
+__device__ __forceinline__ int32_t link(int32_t* parent, int32_t a, int32_t b, int32_t cap, int* flags,
+                                        const ByRank&) {
+  return link_roots_rank(parent, a, b, cap, flags);
 }
 
 // Wavefront sum (64 lanes) by butterfly shuffles.

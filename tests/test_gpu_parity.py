@@ -22,6 +22,8 @@ OPTION_SETS = [
     dict(update_mode=1, block=1024, items=8, grid_cap=3),
     dict(update_mode=0, query_halving=0, compress_every=3, items=2, compress_linked=0),
     dict(update_mode=0, hook=1, items=8, block=512, grid_cap=5),
+    dict(update_mode=0, hook=2),
+    dict(update_mode=0, hook=2, compress_linked=0, items=8, query_halving=0, compress_every=2),
 ]
 
 
@@ -90,7 +92,7 @@ def test_rmat_small(cc, opts):
     run_parity(cc, synth.rmat_stream(scale=16, size_lo=8, size_hi=16, qbatch=1 << 12), opts)
 
 
-@pytest.mark.parametrize("opts", OPTION_SETS[:4], ids=opt_id)
+@pytest.mark.parametrize("opts", OPTION_SETS[:4] + OPTION_SETS[-2:], ids=opt_id)
 def test_grid_small(cc, opts):
     s = synth.grid_stream_cfg(W=256, H=256, batch=1 << 12, qbatch=1 << 10)
     ref = run_parity(cc, s, opts, label_every=4)
@@ -136,8 +138,8 @@ def test_edge_cases(cc, mode):
     g.close()
 
 
-@pytest.mark.parametrize("opts", [dict(update_mode=0), dict(update_mode=1), dict(update_mode=0, hook=1)],
-                         ids=opt_id)
+@pytest.mark.parametrize("opts", [dict(update_mode=0), dict(update_mode=1), dict(update_mode=0, hook=1),
+                                  dict(update_mode=0, hook=2)], ids=opt_id)
 def test_deep_chain(cc, opts):
     # reversed path in one minibatch, then in single-edge minibatches
     n = 1 << 20
@@ -181,6 +183,12 @@ def test_invalid_ids(cc, mode):
 def test_argument_errors(cc):
     g = cc.Graph(16)
     L = cc.lib()
+    assert L.cc_set_option(g.handle, 6, 3) == cc.cc.CC_EINVAL
+    g2 = cc.Graph(16, hook=2, update_mode=1)  # rank linking needs the fused schedule
+    assert L.cc_bulk_update(g2.handle, g2.handle, 0) == cc.cc.CC_OK
+    with pytest.raises(cc.CCError):
+        g2.bulk_update(dev([[1, 2]]))
+    g2.close()
     assert L.cc_bulk_update(g.handle, None, 3) == cc.cc.CC_EINVAL
     assert L.cc_bulk_update(g.handle, None, -1) == cc.cc.CC_EINVAL
     assert L.cc_bulk_query(g.handle, None, 2, None) == cc.cc.CC_EINVAL
@@ -190,7 +198,7 @@ def test_argument_errors(cc):
     g.close()
 
 
-@pytest.mark.parametrize("hook", [0, 1])
+@pytest.mark.parametrize("hook", [0, 1, 2])
 def test_save_load_resume(cc, hook):
     s = synth.rmat_stream(scale=14, size_lo=8, size_hi=13, qbatch=256)
     half = s.num_batches // 2
@@ -198,7 +206,7 @@ def test_save_load_resume(cc, hook):
     for i in range(half):
         a.bulk_update(dev(s.batch(i)))
     img = a.save()
-    b = cc.Graph(s.n, hook=hook, update_mode=1)
+    b = cc.Graph(s.n, hook=hook, update_mode=1 if hook != 2 else 0)
     b.load(img)
     assert b.num_components() == a.num_components()
     for i in range(half, s.num_batches):
