@@ -82,7 +82,14 @@ enum cc_option {
    * device-wide barrier before it gives up, raises the timeout condition
    * (reported by cc_sync as CC_EDEVICE) and makes every block leave the
    * kernel.  Default 2^24 (about one second). */
-  CC_OPT_SPIN_LIMIT = 9
+  CC_OPT_SPIN_LIMIT = 9,
+  /* How finds are done.  0 = every endpoint walks to its root on its own
+   * (with path halving; default).  1 = Bulk-Find (Section 5, Algorithm 4):
+   * all endpoints of a Bulk-Update or Bulk-Query are resolved together, flows
+   * that meet are merged, and every traversed vertex is pointed at its root;
+   * one cooperative launch per bulk operation, about 40 bytes of scratch per
+   * vertex, not available during capture. */
+  CC_OPT_FIND = 10
 };
 
 /* Create a graph on vertices [0, n), 1 <= n <= 2^31 - 1, every vertex its own

@@ -1,0 +1,218 @@
+// Bulk-Find (Section 5, Algorithm 4): the roots of a whole set of vertices S,
+// found together so that flows that meet are merged and every traversed node
+// ends up pointing at its root (path compression shared across the set).
+//
+// One cooperative launch, phases separated by device-wide barriers:
+//   Phase I  (read only): breadth-first search up the forest from S at once.
+//            A vertex joins the frontier only on its first visit (an atomic
+//            test-and-set on the visited bitmap plays mkFrontier/removeDup),
+//            and each visited vertex v records its trail edge (parent[v], v)
+//            (the R_i of the algorithm); roots are collected.
+//   RD       the trail edges leaving each vertex are chained from a list head
+//            per vertex (head[from], next[entry]); allFrom(v) walks that chain.
+//            This serves the response distributor's purpose with O(|trail|)
+//            work and no sort; the lists live in O(n) words like the forest.
+//   Phase II breadth-first search down from the roots along the trail: each
+//            reached vertex is pointed at its root and its chain expanded;
+//            bitmap bits and list heads are cleared on the way, so both are
+//            all-clear again when the kernel ends.
+// The caller's operation then reads the roots with one load per vertex.
+//
+// Bulk-Query: answer = (parent[u] == parent[v]) after the phases.
+// Bulk-Update: after one more barrier, every edge whose endpoints have
+// different roots is linked by CAS (the relabel + filter of Algorithm 2 done
+// with Bulk-Find, as Section 5.2 prescribes for both bulk operations).
+#pragma once
+
+#include "cc_stream_kernels.hpp"
+
+namespace ccdev {
+namespace {
+
+struct BulkFindScratch {
+  uint32_t* visited;  // n bits, all clear at rest
+  int32_t* head;      // n list heads, all -1 at rest
+  int32_t* tto;       // trail: visited vertex of entry k
+  int32_t* tnext;     // trail: next entry with the same parent
+  int32_t* froot;     // roots found (Phase II start)
+  int32_t* f0;        // frontier ping
+  int32_t* f1;        // frontier pong
+  int2* d0;           // Phase II level ping: (vertex, root)
+  int2* d1;           // Phase II level pong
+  unsigned* ctl;      // [0..2] frontier counts (ring), [3] trail count, [4] root count,
+                      // [5..7] level counts (ring), [8..10] barrier
+};
+
+__device__ __forceinline__ bool test_and_set(uint32_t* bits, int32_t v) {
+  const uint32_t m = 1u << (v & 31);
+  return (atomicOr(bits + (v >> 5), m) & m) == 0u;
+}
+
+// Append one item with one atomic per wavefront.
+__device__ __forceinline__ unsigned wave_append(unsigned* counter, bool want) {
+  const unsigned long long mask = __ballot(want);
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((long long)mask) - 1;
+  unsigned base = 0;
+  if (mask && lane == leader) base = atomicAdd(counter, (unsigned)__popcll(mask));
+  base = __shfl(base, leader < 0 ? 0 : leader, 64);
+  const unsigned below = (unsigned)__popcll(mask & ((1ull << lane) - 1ull));
+  return base + below;
+}
+
+// Reserve `cnt` consecutive slots per lane with one atomic per wavefront;
+// returns this lane's first slot.
+__device__ __forceinline__ unsigned wave_reserve(unsigned* counter, unsigned cnt) {
+  const int lane = threadIdx.x & 63;
+  unsigned incl = cnt;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const unsigned y = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += y;
+  }
+  const unsigned total = __shfl(incl, 63, 64);
+  unsigned base = 0;
+  if (lane == 63 && total) base = atomicAdd(counter, total);
+  base = __shfl(base, 63, 64);
+  return base + incl - cnt;
+}
+
+__device__ __forceinline__ unsigned ld_count(unsigned* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_count(unsigned* p, unsigned v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// items: int2 array of `count` pairs (edges or query pairs); each pair's two
+// ids form S.  KIND 0 = Bulk-Update, 1 = Bulk-Query (answers to out).
+template <int KIND, class Ord>
+__global__ void k_bulk_find(int32_t* __restrict__ parent, const int2* __restrict__ items, int64_t count,
+                            int32_t n, uint8_t* __restrict__ out, BulkFindScratch sc,
+                            unsigned long long* __restrict__ slots, int* __restrict__ flags, unsigned spin_limit) {
+  constexpr bool R = is_ranked<Ord>::value;
+  const int64_t gsize = (int64_t)gridDim.x * blockDim.x;
+  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned* bar = sc.ctl + 8;
+  unsigned gen = 0;
+  bool alive = true;
+
+  // level 0: the distinct in-range vertices of S
+  for (int64_t base = 0; base < 2 * count; base += gsize) {
+    const int64_t j = base + gtid;
+    int32_t v = -1;
+    if (j < 2 * count) {
+      const int2 e = items[j >> 1];
+      if (in_range(e, n)) v = (j & 1) ? e.y : e.x;
+      else if ((j & 1) == 0) raise_flag(flags, kFlagRange);
+    }
+    const bool take = v >= 0 && test_and_set(sc.visited, v);
+    const unsigned pos = wave_append(sc.ctl + 0, take);
+    if (take) sc.f0[pos] = v;
+  }
+  alive = grid_sync(bar, gen, flags, spin_limit);
+
+  // Phase I
+  int level = 0;
+  while (alive) {
+    const unsigned c = ld_count(sc.ctl + (level % 3));
+    if (c == 0) break;
+    if (gtid == 0) st_count(sc.ctl + ((level + 2) % 3), 0u);  // read by everyone one level ago
+    const int32_t* cur = (level & 1) ? sc.f1 : sc.f0;
+    int32_t* nxt = (level & 1) ? sc.f0 : sc.f1;
+    unsigned* nct = sc.ctl + ((level + 1) % 3);
+    for (int64_t base = 0; base < (int64_t)c; base += gsize) {
+      const int64_t j = base + gtid;
+      int32_t v = -1, p = -1;
+      if (j < (int64_t)c) {
+        v = cur[j];
+        p = ldp<R>(parent + v);
+      }
+      const bool have = v >= 0;
+      const bool is_root = have && p == v;
+      // trail entry for every visited vertex
+      const unsigned t = wave_append(sc.ctl + 3, have);
+      if (have) {
+        sc.tto[t] = v;
+        if (!is_root) sc.tnext[t] = atomicExch(sc.head + p, (int32_t)t);
+      }
+      const unsigned r = wave_append(sc.ctl + 4, is_root);
+      if (is_root) sc.froot[r] = v;
+      const bool go = have && !is_root && test_and_set(sc.visited, p);
+      const unsigned q = wave_append(nct, go);
+      if (go) nxt[q] = p;
+    }
+    ++level;
+    if (level > n + 1) {
+      raise_flag(flags, kFlagCorrupt);
+      alive = false;
+      break;
+    }
+    alive = grid_sync(bar, gen, flags, spin_limit);
+  }
+
+  // Phase II: down from the roots
+  if (alive) {
+    const unsigned nr = ld_count(sc.ctl + 4);
+    for (int64_t j = gtid; j < (int64_t)nr; j += gsize) sc.d0[j] = make_int2(sc.froot[j], sc.froot[j]);
+    if (gtid == 0) st_count(sc.ctl + 5, nr);
+    alive = grid_sync(bar, gen, flags, spin_limit);
+  }
+  int dl = 0;
+  while (alive) {
+    const unsigned c = ld_count(sc.ctl + 5 + (dl % 3));
+    if (c == 0) break;
+    if (gtid == 0) st_count(sc.ctl + 5 + ((dl + 2) % 3), 0u);
+    const int2* cur = (dl & 1) ? sc.d1 : sc.d0;
+    int2* nxt = (dl & 1) ? sc.d0 : sc.d1;
+    unsigned* nct = sc.ctl + 5 + ((dl + 1) % 3);
+    for (int64_t base = 0; base < (int64_t)c; base += gsize) {
+      const int64_t j = base + gtid;
+      int32_t v = -1, r = -1, k0 = -1;
+      unsigned kids = 0;
+      if (j < (int64_t)c) {
+        const int2 vr = cur[j];
+        v = vr.x;
+        r = vr.y;
+        if (v != r) st(parent + v, r);
+        atomicAnd(sc.visited + (v >> 5), ~(1u << (v & 31)));
+        k0 = sc.head[v];
+        sc.head[v] = -1;
+        for (int32_t k = k0; k >= 0; k = sc.tnext[k]) {
+          if (++kids > (unsigned)n) {
+            raise_flag(flags, kFlagCorrupt);
+            kids = 0;
+            k0 = -1;
+            break;
+          }
+        }
+      }
+      unsigned pos = wave_reserve(nct, kids);
+      for (int32_t k = k0; k >= 0; k = sc.tnext[k]) nxt[pos++] = make_int2(sc.tto[k], r);
+    }
+    ++dl;
+    alive = grid_sync(bar, gen, flags, spin_limit);
+  }
+
+  // the operation itself
+  if (KIND == 1) {
+    for (int64_t i = gtid; i < count; i += gsize) {
+      const int2 e = items[i];
+      uint8_t a = 0;
+      if (in_range(e, n)) a = e.x == e.y || ldp<R>(parent + e.x) == ldp<R>(parent + e.y);
+      out[i] = a;
+    }
+  } else {
+    int links = 0;
+    for (int64_t i = gtid; i < count; i += gsize) {
+      const int2 e = items[i];
+      if (!in_range(e, n) || e.x == e.y) continue;
+      const int32_t ru = ldp<R>(parent + e.x), rv = ldp<R>(parent + e.y);  // roots before any link
+      if (ru != rv) links += link(parent, ru, rv, n, flags, Ord{}) >= 0;
+    }
+    count_links(slots, links);
+  }
+}
+
+}  // namespace
+}  // namespace ccdev

@@ -52,6 +52,7 @@ struct Tuning {
   int grid_cap = 4096;      // CC_OPT_GRID_CAP
   int compress_linked = 1;  // CC_OPT_COMPRESS_LINKED
   int64_t spin_limit = 1 << 24;  // CC_OPT_SPIN_LIMIT
+  int find = 0;                  // CC_OPT_FIND
 };
 
 inline bool set_tuning(Tuning* t, int key, int64_t v) {
@@ -92,6 +93,10 @@ inline bool set_tuning(Tuning* t, int key, int64_t v) {
       if (v < 0 || v > 0xffffffffLL) return false;
       t->spin_limit = v;
       return true;
+    case CC_OPT_FIND:
+      if (v != 0 && v != 1) return false;
+      t->find = (int)v;
+      return true;
     default:
       return false;
   }
@@ -108,6 +113,7 @@ inline bool get_tuning(const Tuning* t, int key, int64_t* v) {
     case CC_OPT_GRID_CAP: *v = t->grid_cap; return true;
     case CC_OPT_COMPRESS_LINKED: *v = t->compress_linked; return true;
     case CC_OPT_SPIN_LIMIT: *v = t->spin_limit; return true;
+    case CC_OPT_FIND: *v = t->find; return true;
     default: return false;
   }
 }

@@ -12,6 +12,7 @@
 #include "../../include/cc.h"
 #include "cc_internal.hpp"
 #include "cc_kernels.hpp"
+#include "cc_bulkfind_kernels.hpp"
 #include "cc_stream_kernels.hpp"
 
 using namespace ccdev;
@@ -54,6 +55,8 @@ struct cc_graph {
   int2* live = nullptr;
   unsigned* live_ctl = nullptr;  // [0] live count, [1] finished blocks, [2..3] same for hooked
   int32_t* hooked = nullptr;     // roots linked by the last fused update (n entries)
+  BulkFindScratch bf{};          // Bulk-Find scratch (allocated on first use)
+  bool bf_ready = false;
   int64_t live_cap = 0;
   int64_t updates = 0;
   bool capturing = false;
@@ -95,10 +98,57 @@ int alloc_hooked(cc_graph* g) {
   return CC_OK;
 }
 
+void free_bulkfind(cc_graph* g) {
+  BulkFindScratch& b = g->bf;
+  (void)hipFree(b.visited);
+  (void)hipFree(b.head);
+  (void)hipFree(b.tto);
+  (void)hipFree(b.tnext);
+  (void)hipFree(b.froot);
+  (void)hipFree(b.f0);
+  (void)hipFree(b.f1);
+  (void)hipFree(b.d0);
+  (void)hipFree(b.d1);
+  (void)hipFree(b.ctl);
+  b = BulkFindScratch{};
+  g->bf_ready = false;
+}
+
+// Bulk-Find keeps its bitmap all clear and its list heads all -1 between
+// calls; this (re)establishes that state.
+void clear_bulkfind(cc_graph* g) {
+  const size_t words = ((size_t)g->n + 31) / 32;
+  hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for((int64_t)words, 256, 4096)), dim3(256), 0, g->stream,
+                     (int32_t*)g->bf.visited, (int32_t)words, 0);
+  hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(g->n, 256, 4096)), dim3(256), 0, g->stream, g->bf.head,
+                     (int32_t)g->n, -1);
+}
+
+int alloc_bulkfind(cc_graph* g) {
+  if (g->bf_ready) return CC_OK;
+  BulkFindScratch& b = g->bf;
+  const size_t n = (size_t)g->n, words = (n + 31) / 32;
+  bool ok = hipMalloc(&b.visited, words * 4) == hipSuccess && hipMalloc(&b.head, n * 4) == hipSuccess &&
+            hipMalloc(&b.tto, n * 4) == hipSuccess && hipMalloc(&b.tnext, n * 4) == hipSuccess &&
+            hipMalloc(&b.froot, n * 4) == hipSuccess && hipMalloc(&b.f0, n * 4) == hipSuccess &&
+            hipMalloc(&b.f1, n * 4) == hipSuccess && hipMalloc(&b.d0, n * 8) == hipSuccess &&
+            hipMalloc(&b.d1, n * 8) == hipSuccess && hipMalloc(&b.ctl, 64) == hipSuccess;
+  if (!ok) {
+    free_bulkfind(g);
+    cc_set_error("Bulk-Find scratch allocation (about 40 bytes per vertex) failed");
+    return CC_ENOMEM;
+  }
+  clear_bulkfind(g);
+  HIP_TRY(hipGetLastError());
+  g->bf_ready = true;
+  return CC_OK;
+}
+
 int launch_init(cc_graph* g) {
   const unsigned blocks = blocks_for((g->n + 3) / 4, 256, 2048);
   hipLaunchKernelGGL(k_init, dim3(blocks), dim3(256), 0, g->stream, g->parent, g->n);
   hipLaunchKernelGGL(k_zero_u64, dim3(4), dim3(256), 0, g->stream, g->slots, kSlots * kSlotStride);
+  if (g->bf_ready) clear_bulkfind(g);
   HIP_TRY(hipGetLastError());
   return CC_OK;
 }
@@ -186,6 +236,41 @@ int read_links(cc_graph* g, unsigned long long* links) {
   for (int i = 0; i < kSlots; ++i) s += h[(size_t)i * kSlotStride];
   *links = s;
   return CC_OK;
+}
+
+template <int KIND, class Ord>
+int launch_bulk_find_t(cc_graph* g, const int2* items, int64_t count, uint8_t* out) {
+  const int block = 256;
+  int per_cu = 0, cus = 0;
+  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bulk_find<KIND, Ord>, block, 0));
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device));
+  int64_t grid = (2 * count + block - 1) / block;
+  grid = std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(grid, (int64_t)per_cu * cus), 1024));
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, g->stream, g->bf.ctl, 16);
+  HIP_TRY(hipGetLastError());
+  int32_t* parent = g->parent;
+  int32_t n = (int32_t)g->n;
+  BulkFindScratch sc = g->bf;
+  unsigned long long* slots = g->slots;
+  int* flags = g->flags;
+  unsigned spin = (unsigned)g->tune.spin_limit;
+  void* args[] = {&parent, &items, &count, &n, &out, &sc, &slots, &flags, &spin};
+  HIP_TRY(hipLaunchCooperativeKernel((const void*)k_bulk_find<KIND, Ord>, dim3((unsigned)grid), dim3(block), args,
+                                     0, g->stream));
+  return CC_OK;
+}
+
+template <int KIND>
+int launch_bulk_find(cc_graph* g, const int2* items, int64_t count, uint8_t* out) {
+  if (g->capturing) {
+    cc_set_error("Bulk-Find is not available while capturing");
+    return CC_EINVAL;
+  }
+  int rc = alloc_bulkfind(g);
+  if (rc != CC_OK) return rc;
+  if (g->tune.hook == 1) return launch_bulk_find_t<KIND, ByHash>(g, items, count, out);
+  if (g->tune.hook == 2) return launch_bulk_find_t<KIND, ByRank>(g, items, count, out);
+  return launch_bulk_find_t<KIND, ById>(g, items, count, out);
 }
 
 }  // namespace
@@ -297,6 +382,11 @@ extern "C" int cc_bulk_update(cc_graph* g, const int32_t* edges, int64_t m) {
   if (m == 0) return CC_OK;
   DeviceGuard dg(g->device);
   const int2* e = reinterpret_cast<const int2*>(edges);
+  if (g->tune.find == 1) {
+    int rc = launch_bulk_find<0>(g, e, m, nullptr);
+    if (rc == CC_OK) g->updates++;
+    return rc;
+  }
   const bool hashed = g->tune.hook == 1, ranked = g->tune.hook == 2;
   if (ranked && g->tune.mode == 1) {
     cc_set_error("cc_bulk_update: union by rank runs with the fused schedule only");
@@ -346,6 +436,7 @@ extern "C" int cc_bulk_query(cc_graph* g, const int32_t* pairs, int64_t q, uint8
   if (q == 0) return CC_OK;
   DeviceGuard dg(g->device);
   const int2* p = reinterpret_cast<const int2*>(pairs);
+  if (g->tune.find == 1) return launch_bulk_find<1>(g, p, q, out);
   const bool ranked = g->tune.hook == 2;
   if (g->tune.query_halving) {
     if (ranked) launch_query_h<true, true>(g, p, q, out);

@@ -65,6 +65,11 @@ def lib():
         L.sg_grid_stream.restype = i64
         L.sg_grid_stream.argtypes = [i64, i64, i64, u64, u64, vp]
         L.sg_apply_perm.argtypes = [vp, i64, vp]
+        L.sg_grid3d_edge_count.restype = i64
+        L.sg_grid3d_edge_count.argtypes = [i64]
+        L.sg_grid3d_stream.restype = i64
+        L.sg_grid3d_stream.argtypes = [i64, u64, vp]
+        L.sg_local_pairs.argtypes = [u64, i64, i64, i64, dbl, vp]
         L.sg_lognormal_counts.argtypes = [u64, i64, dbl, dbl, i64, i64, vp]
         L.sg_poisson_arrivals.argtypes = [u64, i64, dbl, vp]
         _lib = L
@@ -126,6 +131,20 @@ def grid_stream(W: int, H: int, extra: int, lkey: int, skey: int) -> np.ndarray:
     out = np.empty((cnt, 2), np.int32)
     got = lib().sg_grid_stream(W, H, extra, lkey, skey, _ptr(out))
     assert got == cnt
+    return out
+
+
+def grid3d_edges(L: int, skey: int) -> np.ndarray:
+    cnt = int(lib().sg_grid3d_edge_count(L))
+    out = np.empty((cnt, 2), np.int32)
+    assert lib().sg_grid3d_stream(L, skey, _ptr(out)) == cnt
+    return out
+
+
+def local_pairs(k: int, start: int, count: int, n: int, window: int, out=None) -> np.ndarray:
+    if out is None:
+        out = np.empty((count, 2), np.int32)
+    lib().sg_local_pairs(k, start, count, n, float(np.log2(max(2, window))), _ptr(out))
     return out
 
 
@@ -243,6 +262,35 @@ def grid_stream_cfg(W=4096, H=4096, long_frac=0.01, batch=1 << 12, qbatch=1 << 1
     pr = uniform_pairs(key(seed, stream, P_PROBES), 0, probes, n)
     return Stream(name, n, edges, _offsets(sizes), queries, _offsets([qbatch] * nb), pr,
                   dict(kind="grid", W=W, H=H, extra=extra, batch=batch, qbatch=qbatch))
+
+
+def grid3d_stream_cfg(L=256, batch=1 << 22, qbatch=1 << 20, probes=1 << 10, seed=BASE_SEED + 6, stream=0,
+                      name="grid3d") -> Stream:
+    """L^3 6-neighbour mesh (stands in for the paper's 3Dgrid), shuffled,
+    in minibatches of `batch` (the last ragged), each followed by uniform pairs."""
+    n = L ** 3
+    edges = grid3d_edges(L, key(seed, stream, P_SHUFFLE))
+    m = edges.shape[0]
+    nb = (m + batch - 1) // batch
+    sizes = [batch] * (nb - 1) + [m - batch * (nb - 1)]
+    queries = uniform_pairs(key(seed, stream, P_QUERIES), 0, nb * qbatch, n)
+    pr = uniform_pairs(key(seed, stream, P_PROBES), 0, probes, n)
+    return Stream(name, n, edges, _offsets(sizes), queries, _offsets([qbatch] * nb), pr,
+                  dict(kind="grid3d", L=L, batch=batch, qbatch=qbatch))
+
+
+def local_stream(n=1 << 24, degree=5, window=1 << 12, batch=1 << 22, qbatch=1 << 20, probes=1 << 10,
+                 seed=BASE_SEED + 7, stream=0, name="local") -> Stream:
+    """degree * n locality-biased random edges (stands in for the paper's
+    local5 / local16 "small separator" graphs), in minibatches of `batch`."""
+    m = degree * n
+    edges = local_pairs(key(seed, stream, P_EDGES), 0, m, n, window)
+    nb = (m + batch - 1) // batch
+    sizes = [batch] * (nb - 1) + [m - batch * (nb - 1)]
+    queries = uniform_pairs(key(seed, stream, P_QUERIES), 0, nb * qbatch, n)
+    pr = uniform_pairs(key(seed, stream, P_PROBES), 0, probes, n)
+    return Stream(name, n, edges, _offsets(sizes), queries, _offsets([qbatch] * nb), pr,
+                  dict(kind="local", degree=degree, window=window, batch=batch, qbatch=qbatch))
 
 
 def multi_graph_sizes(G=1024, mu=14.0, sigma=2.0, lo=1 << 10, hi=1 << 20,

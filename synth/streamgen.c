@@ -180,6 +180,55 @@ int64_t sg_grid_stream(int64_t W, int64_t H, int64_t extra, uint64_t lkey, uint6
   return nh + nv + extra;
 }
 
+/* Number of edges of an L x L x L 6-neighbour mesh. */
+int64_t sg_grid3d_edge_count(int64_t L) { return 3 * L * L * (L - 1); }
+
+/*
+ * L x L x L mesh, ids x + L*(y + L*z): edges along x, then y, then z, each
+ * joining a vertex to its +1 neighbour on that axis; then shuffled with skey.
+ * out must hold sg_grid3d_edge_count(L) pairs.
+ */
+int64_t sg_grid3d_stream(int64_t L, uint64_t skey, int32_t* out) {
+  const int64_t per = L * L * (L - 1);
+#pragma omp parallel for schedule(static)
+  for (int64_t k = 0; k < per; ++k) {
+    /* k indexes (a, b, c) with a in [0, L-1) the step coordinate */
+    const int64_t a = k % (L - 1), r = k / (L - 1), b = r % L, c = r / L;
+    /* axis x: (a, b, c)-(a+1, b, c) */
+    out[2 * k] = (int32_t)(a + L * (b + L * c));
+    out[2 * k + 1] = (int32_t)(a + 1 + L * (b + L * c));
+    /* axis y: (b, a, c)-(b, a+1, c) */
+    out[2 * (per + k)] = (int32_t)(b + L * (a + L * c));
+    out[2 * (per + k) + 1] = (int32_t)(b + L * (a + 1 + L * c));
+    /* axis z: (b, c, a)-(b, c, a+1) */
+    out[2 * (2 * per + k)] = (int32_t)(b + L * (c + L * a));
+    out[2 * (2 * per + k) + 1] = (int32_t)(b + L * (c + L * (a + 1)));
+  }
+  sg_shuffle_pairs(skey, 3 * per, out);
+  return 3 * per;
+}
+
+/*
+ * Locality-biased random edges (small separators): edge i joins
+ * u = below(draw(key, 3i), n) and v = (u + s * d) mod n with
+ * d = floor(2^(U * lg)) for U = unit(draw(key, 3i+1)), lg = log2(window),
+ * and s = +1 or -1 from draw(key, 3i+2): most edges are short, a few span
+ * up to `window` ids.
+ */
+void sg_local_pairs(uint64_t key, int64_t start, int64_t count, int64_t n, double lg, int32_t* out) {
+#pragma omp parallel for schedule(static)
+  for (int64_t k = 0; k < count; ++k) {
+    const uint64_t i = (uint64_t)(start + k);
+    const int64_t u = sg_below(sg_draw(key, 3 * i), (uint64_t)n);
+    const int64_t d = (int64_t)floor(exp2(sg_unit(sg_draw(key, 3 * i + 1)) * lg));
+    const int64_t sgn = (sg_draw(key, 3 * i + 2) >> 63) ? 1 : -1;
+    int64_t v = (u + sgn * (d % n)) % n;
+    if (v < 0) v += n;
+    out[2 * k] = (int32_t)u;
+    out[2 * k + 1] = (int32_t)v;
+  }
+}
+
 /* Map both ids of count pairs through perm, in place. */
 void sg_apply_perm(const int32_t* perm, int64_t count, int32_t* pairs) {
 #pragma omp parallel for schedule(static)

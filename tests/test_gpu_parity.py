@@ -24,6 +24,8 @@ OPTION_SETS = [
     dict(update_mode=0, hook=1, items=8, block=512, grid_cap=5),
     dict(update_mode=0, hook=2),
     dict(update_mode=0, hook=2, compress_linked=0, items=8, query_halving=0, compress_every=2),
+    dict(find=1),
+    dict(find=1, hook=2),
 ]
 
 
@@ -97,6 +99,16 @@ def test_grid_small(cc, opts):
     s = synth.grid_stream_cfg(W=256, H=256, batch=1 << 12, qbatch=1 << 10)
     ref = run_parity(cc, s, opts, label_every=4)
     assert ref.num_components() >= 1
+
+
+@pytest.mark.parametrize("which", ["grid3d", "local"])
+@pytest.mark.parametrize("opts", [dict(), dict(hook=2), dict(update_mode=1)], ids=opt_id)
+def test_more_workload_shapes(cc, which, opts):
+    if which == "grid3d":
+        s = synth.grid3d_stream_cfg(L=40, batch=1 << 13, qbatch=1 << 10)
+    else:
+        s = synth.local_stream(n=1 << 16, degree=5, window=1 << 10, batch=1 << 15, qbatch=1 << 10)
+    run_parity(cc, s, opts, label_every=3)
 
 
 @pytest.mark.parametrize("mode", [0, 1])
@@ -243,4 +255,44 @@ def test_order_independence_and_reset(cc):
         for b in np.array_split(e, 5):
             g.bulk_update(dev(b))
         np.testing.assert_array_equal(g.labels().cpu().numpy(), want)
+    g.close()
+
+
+def test_bulk_find_worked_example(cc):
+    """Section 5's example: a tree rooted at 19 in which the finds of 1 and 7
+    meet at 4 (1 -> 2 -> 4 and 7 -> 8 -> 9 -> 4) and the find of 3 joins 1's
+    flow at 2.  After Bulk-Find of {1, 3, 4, 7} every traversed vertex points
+    straight at the root (Phase II).  The figure's full tree is not in the
+    text; the fragment given there is used, with 4 -> 19.  Loaded as a rank
+    forest image, which accepts any acyclic parent array."""
+    n = 24
+    par = np.arange(n, dtype=np.int32)
+    for c, p in ((1, 2), (3, 2), (2, 4), (7, 8), (8, 9), (9, 4), (4, 19)):
+        par[c] = p
+    img = bytearray(np.array([n, 7], np.int64).tobytes() + par.tobytes())
+    g = cc.Graph(n, hook=2, find=1)
+    g.load(img)
+    ans = g.bulk_query(dev([[1, 3], [4, 7], [1, 19], [5, 19]])).cpu().numpy()
+    np.testing.assert_array_equal(ans, [1, 1, 1, 0])
+    after = np.frombuffer(bytes(g.save()), np.int32, offset=16) & ((1 << 27) - 1)
+    for v in (1, 2, 3, 4, 7, 8, 9):
+        assert after[v] == 19, (v, after[v])
+    assert after[5] == 5 and after[19] == 19
+    assert g.sync() == cc.cc.CC_OK
+    g.close()
+
+
+def test_bulk_find_compresses_every_endpoint(cc):
+    s = synth.rmat_stream(scale=15, size_lo=10, size_hi=14, qbatch=1 << 12)
+    g = cc.Graph(s.n, find=1, hook=2)
+    ref = oracle.UnionFind(s.n)
+    for i in range(s.num_batches):
+        g.bulk_update(dev(s.batch(i)))
+        ref.bulk_update(s.batch(i))
+        q = s.query(i)
+        np.testing.assert_array_equal(g.bulk_query(dev(q)).cpu().numpy(), ref.bulk_query(q))
+        par = np.frombuffer(bytes(g.save()), np.int32, offset=16) & ((1 << 27) - 1)
+        ends = np.unique(q)
+        assert (par[par[ends]] == par[ends]).all(), "a queried vertex does not point at its root"
+    np.testing.assert_array_equal(g.labels().cpu().numpy(), ref.labels())
     g.close()

@@ -61,3 +61,21 @@ def test_multi_graph_recipe(built_libs):
         assert s.num_batches == 4 and s.eoff[-1] == 8 * n
         assert s.edges.max() < n and (np.diff(s.eoff) >= 0).all()
     assert s1.meta["kind"] == "rmat" and s0.meta["kind"] == "uniform"
+
+
+def test_grid3d_and_local_recipes(built_libs):
+    import oracle
+    L = 12
+    e = synth.grid3d_edges(L, synth.key(1, 0, synth.P_SHUFFLE))
+    assert e.shape[0] == 3 * L * L * (L - 1)
+    d = np.abs(e[:, 0].astype(np.int64) - e[:, 1])
+    assert set(d.tolist()) == {1, L, L * L}
+    assert len({tuple(sorted(x)) for x in e.tolist()}) == e.shape[0]  # no repeats
+    uf = oracle.UnionFind(L ** 3)
+    uf.bulk_update(e)
+    assert uf.num_components() == 1  # closed form: the mesh is connected
+    n, w = 1 << 14, 1 << 6
+    s = synth.local_stream(n=n, degree=5, window=w, batch=1 << 12, qbatch=64)
+    dd = np.abs(s.edges[:, 0].astype(np.int64) - s.edges[:, 1])
+    dd = np.minimum(dd, n - dd)
+    assert len(s.edges) == 5 * n and dd.max() < w and s.edges.min() >= 0 and s.edges.max() < n
