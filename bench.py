@@ -493,12 +493,60 @@ def run_serve(args):
     return res
 
 
+def run_components(args):
+    """Number of components against the fraction of the stream consumed, for
+    each workload shape at n = 2^24 (the measurement behind Fig. 2)."""
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_1602_05232_amd as ccgpu
+    from paper_1602_05232_amd import tuning
+
+    shapes = {
+        "random (ER, 5 edges/vertex)": lambda: synth.er_stream(n=1 << 24, batches=80, batch=(5 << 24) // 80,
+                                                               qbatch=1, probes=0),
+        "rmat (scale 24, EF 16)": lambda: synth.rmat_stream(scale=24, qbatch=1, probes=0),
+        "grid3d (256^3)": lambda: synth.grid3d_stream_cfg(L=256, batch=1 << 21, qbatch=1, probes=0),
+        "local5 (window 2^12)": lambda: synth.local_stream(n=1 << 24, degree=5, window=1 << 12, batch=1 << 21,
+                                                           qbatch=1, probes=0),
+        "local16 (window 2^12)": lambda: synth.local_stream(n=1 << 24, degree=16, window=1 << 12,
+                                                            batch=1 << 22, qbatch=1, probes=0),
+    }
+    traces, total_t, total_e = {}, 0.0, 0
+    for name, make in shapes.items():
+        s = make()
+        E = torch.from_numpy(s.edges).cuda()
+        g = ccgpu.Graph(s.n, **tuning.plain_options(s.n, "rmat"))
+        g.reserve(int(np.diff(s.eoff).max()))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pts = [(0.0, s.n)]
+        for i in range(s.num_batches):
+            g.bulk_update(E[int(s.eoff[i]):int(s.eoff[i + 1])])
+            pts.append((float(s.eoff[i + 1]) / len(s.edges), g.num_components()))
+        total_t += time.perf_counter() - t0
+        total_e += len(s.edges)
+        assert g.sync() == 0
+        traces[name] = pts
+        log("%s: %d edges, components at end %d" % (name, len(s.edges), pts[-1][1]))
+        g.close()
+        del E
+        torch.cuda.empty_cache()
+    res = result(total_e / total_t, 1, 0, total_t, {"workload": "component-trace", "n": 1 << 24,
+                                                      "shapes": list(shapes)})
+    res["unit"] = "edges/s (one count read per minibatch)"
+    res["traces"] = traces
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rmat24", choices=["rmat24", "grid4096", "batched1024", "serve64"])
+    ap.add_argument("--workload", default="rmat24",
+                    choices=["rmat24", "grid4096", "batched1024", "serve64", "components"])
     ap.add_argument("--requests", type=int, default=1024, help="requests of the serving trace")
     ap.add_argument("--serve-scale", type=int, default=22, help="R-MAT scale of each served graph")
     ap.add_argument("--scale", type=int, default=24, help="R-MAT scale of the rmat24 workload")
@@ -520,7 +568,7 @@ def main():
         import __graft_entry__
         __graft_entry__.build()
     res = {"rmat24": run_rmat, "grid4096": run_grid, "batched1024": run_batched,
-           "serve64": run_serve}[args.workload](args)
+           "serve64": run_serve, "components": run_components}[args.workload](args)
     print(json.dumps(res), flush=True)
 
 

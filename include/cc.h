@@ -87,7 +87,7 @@ enum cc_option {
    * (with path halving; default).  1 = Bulk-Find (Section 5, Algorithm 4):
    * all endpoints of a Bulk-Update or Bulk-Query are resolved together, flows
    * that meet are merged, and every traversed vertex is pointed at its root;
-   * one cooperative launch per bulk operation, about 40 bytes of scratch per
+   * one cooperative launch per bulk operation, about 12 bytes of scratch per
    * vertex, not available during capture. */
   CC_OPT_FIND = 10
 };

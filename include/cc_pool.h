@@ -70,6 +70,11 @@ int cc_pool_reset_all(cc_pool* p);
 int64_t cc_pool_graph_vertices(const cc_pool* p, int32_t id);   /* 0 if no such graph */
 int64_t cc_pool_free_vertices(const cc_pool* p);               /* total free entries */
 int64_t cc_pool_largest_gap(const cc_pool* p);                 /* largest addable n */
+/* Arena offset of graph `id` (-1 if no such graph), and the free ranges:
+ * up to max (base, length) pairs in ascending base order; returns how many
+ * free ranges there are.  For callers that plan admissions and evictions. */
+int64_t cc_pool_graph_base(const cc_pool* p, int32_t id);
+int32_t cc_pool_gaps(const cc_pool* p, int64_t* bases, int64_t* lengths, int32_t max);
 
 /* Run the operations: those on one graph in list order, different graphs
  * together, with one kernel launch per round (round r holds every graph's

@@ -65,6 +65,8 @@ POOL_SIGNATURES = {
     "cc_pool_graph_vertices": (_i64, [_vp, _i32]),
     "cc_pool_free_vertices": (_i64, [_vp]),
     "cc_pool_largest_gap": (_i64, [_vp]),
+    "cc_pool_graph_base": (_i64, [_vp, _i32]),
+    "cc_pool_gaps": (_i32, [_vp, _vp, _vp, _i32]),
     "cc_pool_run": (_i32, [_vp, _vp, _i32]),
     "cc_pool_labels": (_i32, [_vp, _i32, _vp]),
     "cc_pool_num_components": (_i32, [_vp, _i32, ctypes.POINTER(_i64)]),
@@ -368,6 +370,26 @@ class Pool:
 
     def largest_gap(self) -> int:
         return int(lib().cc_pool_largest_gap(self._h))
+
+    def gaps(self):
+        """Free ranges as (base, length), ascending."""
+        k = int(lib().cc_pool_gaps(self._h, None, None, 0))
+        b = (ctypes.c_int64 * max(1, k))()
+        ln = (ctypes.c_int64 * max(1, k))()
+        lib().cc_pool_gaps(self._h, b, ln, k)
+        return [(b[i], ln[i]) for i in range(k)]
+
+    def gaps_after_removing(self, gids):
+        """Lengths of the free ranges if the graphs `gids` were removed."""
+        ranges = sorted(self.gaps() + [(int(lib().cc_pool_graph_base(self._h, int(g))), self.vertices(g))
+                                       for g in gids])
+        merged = []
+        for b, ln in ranges:
+            if merged and merged[-1][0] + merged[-1][1] == b:
+                merged[-1] = (merged[-1][0], merged[-1][1] + ln)
+            else:
+                merged.append((b, ln))
+        return [ln for _, ln in merged]
 
     def run(self, ops):
         arr = (CcOp * max(1, len(ops)))()

@@ -6,16 +6,18 @@
 //   Phase I  (read only): breadth-first search up the forest from S at once.
 //            A vertex joins the frontier only on its first visit (an atomic
 //            test-and-set on the visited bitmap plays mkFrontier/removeDup),
-//            and each visited vertex v records its trail edge (parent[v], v)
-//            (the R_i of the algorithm); roots are collected.
-//   RD       the trail edges leaving each vertex are chained from a list head
-//            per vertex (head[from], next[entry]); allFrom(v) walks that chain.
-//            This serves the response distributor's purpose with O(|trail|)
-//            work and no sort; the lists live in O(n) words like the forest.
-//   Phase II breadth-first search down from the roots along the trail: each
-//            reached vertex is pointed at its root and its chain expanded;
-//            bitmap bits and list heads are cleared on the way, so both are
-//            all-clear again when the kernel ends.
+//            and every visited vertex is recorded once in the trail (the
+//            R_i of the algorithm: its edge to the parent is parent[v] itself,
+//            which Phase I does not change).
+//   Phase II every trail vertex is pointed at its root.  The paper does this
+//            top-down from the roots, expanding each vertex's recorded
+//            children through the response distributor; on the GPU a root
+//            can have millions of such children, and expanding one vertex's
+//            list is serial, so Phase II here points each trail vertex at its
+//            grandparent, round after round, until a round changes nothing
+//            (pointer jumping restricted to the trail: O(|trail| log h)
+//            work, log h rounds).  The visited bits are then cleared, so the
+//            bitmap is all clear again when the kernel ends.
 // The caller's operation then reads the roots with one load per vertex.
 //
 // Bulk-Query: answer = (parent[u] == parent[v]) after the phases.
@@ -31,16 +33,11 @@ namespace {
 
 struct BulkFindScratch {
   uint32_t* visited;  // n bits, all clear at rest
-  int32_t* head;      // n list heads, all -1 at rest
-  int32_t* tto;       // trail: visited vertex of entry k
-  int32_t* tnext;     // trail: next entry with the same parent
-  int32_t* froot;     // roots found (Phase II start)
+  int32_t* trail;     // every visited vertex once
   int32_t* f0;        // frontier ping
   int32_t* f1;        // frontier pong
-  int2* d0;           // Phase II level ping: (vertex, root)
-  int2* d1;           // Phase II level pong
-  unsigned* ctl;      // [0..2] frontier counts (ring), [3] trail count, [4] root count,
-                      // [5..7] level counts (ring), [8..10] barrier
+  unsigned* ctl;      // [0..2] frontier counts (ring), [3] trail count,
+                      // [5..7] Phase II change flags (ring), [8..10] barrier
 };
 
 __device__ __forceinline__ bool test_and_set(uint32_t* bits, int32_t v) {
@@ -58,23 +55,6 @@ __device__ __forceinline__ unsigned wave_append(unsigned* counter, bool want) {
   base = __shfl(base, leader < 0 ? 0 : leader, 64);
   const unsigned below = (unsigned)__popcll(mask & ((1ull << lane) - 1ull));
   return base + below;
-}
-
-// Reserve `cnt` consecutive slots per lane with one atomic per wavefront;
-// returns this lane's first slot.
-__device__ __forceinline__ unsigned wave_reserve(unsigned* counter, unsigned cnt) {
-  const int lane = threadIdx.x & 63;
-  unsigned incl = cnt;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const unsigned y = __shfl_up(incl, off, 64);
-    if (lane >= off) incl += y;
-  }
-  const unsigned total = __shfl(incl, 63, 64);
-  unsigned base = 0;
-  if (lane == 63 && total) base = atomicAdd(counter, total);
-  base = __shfl(base, 63, 64);
-  return base + incl - cnt;
 }
 
 __device__ __forceinline__ unsigned ld_count(unsigned* p) {
@@ -130,14 +110,8 @@ __global__ void k_bulk_find(int32_t* __restrict__ parent, const int2* __restrict
       }
       const bool have = v >= 0;
       const bool is_root = have && p == v;
-      // trail entry for every visited vertex
       const unsigned t = wave_append(sc.ctl + 3, have);
-      if (have) {
-        sc.tto[t] = v;
-        if (!is_root) sc.tnext[t] = atomicExch(sc.head + p, (int32_t)t);
-      }
-      const unsigned r = wave_append(sc.ctl + 4, is_root);
-      if (is_root) sc.froot[r] = v;
+      if (have) sc.trail[t] = v;
       const bool go = have && !is_root && test_and_set(sc.visited, p);
       const unsigned q = wave_append(nct, go);
       if (go) nxt[q] = p;
@@ -151,47 +125,34 @@ __global__ void k_bulk_find(int32_t* __restrict__ parent, const int2* __restrict
     alive = grid_sync(bar, gen, flags, spin_limit);
   }
 
-  // Phase II: down from the roots
-  if (alive) {
-    const unsigned nr = ld_count(sc.ctl + 4);
-    for (int64_t j = gtid; j < (int64_t)nr; j += gsize) sc.d0[j] = make_int2(sc.froot[j], sc.froot[j]);
-    if (gtid == 0) st_count(sc.ctl + 5, nr);
-    alive = grid_sync(bar, gen, flags, spin_limit);
-  }
-  int dl = 0;
-  while (alive) {
-    const unsigned c = ld_count(sc.ctl + 5 + (dl % 3));
-    if (c == 0) break;
-    if (gtid == 0) st_count(sc.ctl + 5 + ((dl + 2) % 3), 0u);
-    const int2* cur = (dl & 1) ? sc.d1 : sc.d0;
-    int2* nxt = (dl & 1) ? sc.d0 : sc.d1;
-    unsigned* nct = sc.ctl + 5 + ((dl + 1) % 3);
-    for (int64_t base = 0; base < (int64_t)c; base += gsize) {
-      const int64_t j = base + gtid;
-      int32_t v = -1, r = -1, k0 = -1;
-      unsigned kids = 0;
-      if (j < (int64_t)c) {
-        const int2 vr = cur[j];
-        v = vr.x;
-        r = vr.y;
-        if (v != r) st(parent + v, r);
-        atomicAnd(sc.visited + (v >> 5), ~(1u << (v & 31)));
-        k0 = sc.head[v];
-        sc.head[v] = -1;
-        for (int32_t k = k0; k >= 0; k = sc.tnext[k]) {
-          if (++kids > (unsigned)n) {
-            raise_flag(flags, kFlagCorrupt);
-            kids = 0;
-            k0 = -1;
-            break;
-          }
-        }
+  // Phase II: pointer jumping over the trail until every trail vertex points
+  // at its root.  Round r raises change flag r % 3 and clears flag (r+1) % 3,
+  // which everyone read before arriving at the barrier of round r-1.
+  const unsigned lam = ld_count(sc.ctl + 3);
+  for (int round = 0; alive; ++round) {
+    if (gtid == 0) st_count(sc.ctl + 5 + ((round + 1) % 3), 0u);
+    bool moved = false;
+    for (int64_t t = gtid; t < (int64_t)lam; t += gsize) {
+      const int32_t v = sc.trail[t];
+      const int32_t p = ldp<R>(parent + v);
+      if (p == v) continue;
+      const int32_t g = ldp<R>(parent + p);
+      if (g != p) {
+        st(parent + v, g);
+        moved = true;
       }
-      unsigned pos = wave_reserve(nct, kids);
-      for (int32_t k = k0; k >= 0; k = sc.tnext[k]) nxt[pos++] = make_int2(sc.tto[k], r);
     }
-    ++dl;
+    if (moved) st_count(sc.ctl + 5 + (round % 3), 1u);
     alive = grid_sync(bar, gen, flags, spin_limit);
+    if (!alive || ld_count(sc.ctl + 5 + (round % 3)) == 0u) break;
+    if (round > 64) {  // deeper than any forest of 2^31 vertices after this many halvings
+      raise_flag(flags, kFlagCorrupt);
+      alive = false;
+    }
+  }
+  for (int64_t t = gtid; t < (int64_t)lam; t += gsize) {
+    const int32_t v = sc.trail[t];
+    atomicAnd(sc.visited + (v >> 5), ~(1u << (v & 31)));
   }
 
   // the operation itself

@@ -101,41 +101,32 @@ int alloc_hooked(cc_graph* g) {
 void free_bulkfind(cc_graph* g) {
   BulkFindScratch& b = g->bf;
   (void)hipFree(b.visited);
-  (void)hipFree(b.head);
-  (void)hipFree(b.tto);
-  (void)hipFree(b.tnext);
-  (void)hipFree(b.froot);
+  (void)hipFree(b.trail);
   (void)hipFree(b.f0);
   (void)hipFree(b.f1);
-  (void)hipFree(b.d0);
-  (void)hipFree(b.d1);
   (void)hipFree(b.ctl);
   b = BulkFindScratch{};
   g->bf_ready = false;
 }
 
-// Bulk-Find keeps its bitmap all clear and its list heads all -1 between
-// calls; this (re)establishes that state.
+// Bulk-Find keeps its visited bitmap all clear between calls; this
+// (re)establishes that state.
 void clear_bulkfind(cc_graph* g) {
   const size_t words = ((size_t)g->n + 31) / 32;
   hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for((int64_t)words, 256, 4096)), dim3(256), 0, g->stream,
                      (int32_t*)g->bf.visited, (int32_t)words, 0);
-  hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(g->n, 256, 4096)), dim3(256), 0, g->stream, g->bf.head,
-                     (int32_t)g->n, -1);
 }
 
 int alloc_bulkfind(cc_graph* g) {
   if (g->bf_ready) return CC_OK;
   BulkFindScratch& b = g->bf;
   const size_t n = (size_t)g->n, words = (n + 31) / 32;
-  bool ok = hipMalloc(&b.visited, words * 4) == hipSuccess && hipMalloc(&b.head, n * 4) == hipSuccess &&
-            hipMalloc(&b.tto, n * 4) == hipSuccess && hipMalloc(&b.tnext, n * 4) == hipSuccess &&
-            hipMalloc(&b.froot, n * 4) == hipSuccess && hipMalloc(&b.f0, n * 4) == hipSuccess &&
-            hipMalloc(&b.f1, n * 4) == hipSuccess && hipMalloc(&b.d0, n * 8) == hipSuccess &&
-            hipMalloc(&b.d1, n * 8) == hipSuccess && hipMalloc(&b.ctl, 64) == hipSuccess;
+  bool ok = hipMalloc(&b.visited, words * 4) == hipSuccess && hipMalloc(&b.trail, n * 4) == hipSuccess &&
+            hipMalloc(&b.f0, n * 4) == hipSuccess && hipMalloc(&b.f1, n * 4) == hipSuccess &&
+            hipMalloc(&b.ctl, 64) == hipSuccess;
   if (!ok) {
     free_bulkfind(g);
-    cc_set_error("Bulk-Find scratch allocation (about 40 bytes per vertex) failed");
+    cc_set_error("Bulk-Find scratch allocation (about 12 bytes per vertex) failed");
     return CC_ENOMEM;
   }
   clear_bulkfind(g);

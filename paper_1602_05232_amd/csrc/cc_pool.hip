@@ -51,6 +51,9 @@ struct cc_pool {
   int* flags = nullptr;
   std::vector<PoolGraph> graphs;
   std::map<int64_t, int64_t> gaps;  // base -> length of each free range
+  int32_t* staging = nullptr;       // device image buffer for save / load
+  int64_t staging_cap = 0;
+  unsigned long long* check = nullptr;  // [0] bad entries, [1] roots (image check)
   RingSlot ring[kRing];
   int ring_next = 0;
   cc::Tuning tune;
@@ -206,6 +209,8 @@ extern "C" int cc_pool_destroy(cc_pool* p) {
   (void)hipFree(p->arena);
   (void)hipFree(p->glinks);
   (void)hipFree(p->flags);
+  (void)hipFree(p->staging);
+  (void)hipFree(p->check);
   delete p;
   return CC_OK;
 }
@@ -308,6 +313,23 @@ extern "C" int64_t cc_pool_free_vertices(const cc_pool* p) {
   int64_t s = 0;
   for (const auto& kv : p->gaps) s += kv.second;
   return s;
+}
+
+extern "C" int64_t cc_pool_graph_base(const cc_pool* p, int32_t id) {
+  return valid_graph(p, id) ? p->graphs[(size_t)id].base : -1;
+}
+
+extern "C" int32_t cc_pool_gaps(const cc_pool* p, int64_t* bases, int64_t* lengths, int32_t max) {
+  if (!p) return 0;
+  int32_t i = 0;
+  for (const auto& kv : p->gaps) {
+    if (i < max && bases && lengths) {
+      bases[i] = kv.first;
+      lengths[i] = kv.second;
+    }
+    ++i;
+  }
+  return i;
 }
 
 extern "C" int64_t cc_pool_largest_gap(const cc_pool* p) {
@@ -416,6 +438,26 @@ extern "C" int cc_pool_labels(cc_pool* p, int32_t id, int32_t* out) {
 }
 
 namespace {
+int ensure_staging(cc_pool* p, int64_t n) {
+  if (!p->check && hipMalloc(&p->check, 16) != hipSuccess) {
+    p->check = nullptr;
+    cc_set_error("image check buffer allocation failed");
+    return CC_ENOMEM;
+  }
+  if (p->staging_cap >= n) return CC_OK;
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  (void)hipFree(p->staging);
+  p->staging = nullptr;
+  p->staging_cap = 0;
+  if (hipMalloc(&p->staging, (size_t)n * 4) != hipSuccess) {
+    p->staging = nullptr;
+    cc_set_error("image staging allocation failed");
+    return CC_ENOMEM;
+  }
+  p->staging_cap = n;
+  return CC_OK;
+}
+
 int read_graph_links(cc_pool* p, int32_t id, unsigned long long* links) {
   HIP_TRY(hipMemcpyAsync(links, p->glinks + (size_t)id * kPoolLinkStride, 8, hipMemcpyDeviceToHost, p->stream));
   HIP_TRY(hipStreamSynchronize(p->stream));
@@ -463,16 +505,18 @@ extern "C" int cc_pool_save(cc_pool* p, int32_t id, void* host_buf) {
   if (!valid_graph(p, id) || !host_buf) return CC_EINVAL;
   DeviceGuard dg(p->device);
   const PoolGraph& g = p->graphs[(size_t)id];
+  int rc = ensure_staging(p, g.n);
+  if (rc != CC_OK) return rc;
   unsigned long long links = 0;
-  int rc = read_graph_links(p, id, &links);
+  rc = read_graph_links(p, id, &links);
   if (rc != CC_OK) return rc;
   int64_t hdr[2] = {g.n, (int64_t)links};
   memcpy(host_buf, hdr, 16);
-  int32_t* par = reinterpret_cast<int32_t*>((char*)host_buf + 16);
-  HIP_TRY(hipMemcpyAsync(par, p->arena + g.base, (size_t)g.n * 4, hipMemcpyDeviceToHost, p->stream));
+  hipLaunchKernelGGL(k_to_local, dim3(blocks_for(g.n, 256, 4096)), dim3(256), 0, p->stream, p->arena,
+                     (int32_t)g.base, (int32_t)g.n, p->staging);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync((char*)host_buf + 16, p->staging, (size_t)g.n * 4, hipMemcpyDeviceToHost, p->stream));
   HIP_TRY(hipStreamSynchronize(p->stream));
-  const int32_t base = (int32_t)g.base;
-  for (int64_t v = 0; v < g.n; ++v) par[v] -= base;
   return CC_OK;
 }
 
@@ -486,27 +530,31 @@ extern "C" int cc_pool_load(cc_pool* p, int32_t id, const void* host_buf) {
     cc_set_error("cc_pool_load: image has n=%lld, graph has n=%lld", (long long)hdr[0], (long long)g.n);
     return CC_EINVAL;
   }
-  const int32_t* par = reinterpret_cast<const int32_t*>((const char*)host_buf + 16);
-  int64_t roots = 0;
-  if (!cc::check_forest(par, g.n, p->tune.hook, &roots) || hdr[1] != g.n - roots) {
+  int rc = ensure_staging(p, g.n);
+  if (rc != CC_OK) return rc;
+  const unsigned blocks = blocks_for(g.n, 256, 4096);
+  HIP_TRY(hipMemcpyAsync(p->staging, (const char*)host_buf + 16, (size_t)g.n * 4, hipMemcpyHostToDevice,
+                         p->stream));
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, p->stream, p->check, 2);
+  if (p->tune.hook == 1)
+    hipLaunchKernelGGL(k_check_image<true>, dim3(blocks), dim3(256), 0, p->stream, p->staging, (int32_t)g.n,
+                       p->check);
+  else
+    hipLaunchKernelGGL(k_check_image<false>, dim3(blocks), dim3(256), 0, p->stream, p->staging, (int32_t)g.n,
+                       p->check);
+  HIP_TRY(hipGetLastError());
+  unsigned long long res[2] = {0, 0};
+  HIP_TRY(hipMemcpyAsync(res, p->check, 16, hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  if (res[0] != 0 || hdr[1] != g.n - (int64_t)res[1]) {
     cc_set_error("cc_pool_load: image is not a forest under the pool's linking order");
     return CC_ECORRUPT;
   }
-  int32_t* staging = nullptr;
-  HIP_TRY(hipHostMalloc((void**)&staging, (size_t)g.n * 4, hipHostMallocDefault));
-  const int32_t base = (int32_t)g.base;
-  for (int64_t v = 0; v < g.n; ++v) staging[v] = par[v] + base;
   unsigned long long links = (unsigned long long)hdr[1];
-  hipError_t e = hipStreamSynchronize(p->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(p->arena + g.base, staging, (size_t)g.n * 4, hipMemcpyHostToDevice, p->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(p->glinks + (size_t)id * kPoolLinkStride, &links, 8, hipMemcpyHostToDevice, p->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
-  (void)hipHostFree(staging);
-  if (e != hipSuccess) {
-    cc_set_error("cc_pool_load: %s", hipGetErrorString(e));
-    return CC_EDEVICE;
-  }
+  hipLaunchKernelGGL(k_place, dim3(blocks), dim3(256), 0, p->stream, p->staging, (int32_t)g.base, (int32_t)g.n,
+                     p->arena);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(p->glinks + (size_t)id * kPoolLinkStride, &links, 8, hipMemcpyHostToDevice, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
   return CC_OK;
 }

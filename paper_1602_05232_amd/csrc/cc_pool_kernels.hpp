@@ -154,5 +154,40 @@ __global__ void k_pool_labels_gather(const int32_t* __restrict__ arena, int32_t 
     out[v] = out[find_read(arena, base + v, n, flags) - base];
 }
 
+// Image conversion for save / load: arena ids <-> graph-local ids.
+__global__ void k_to_local(const int32_t* __restrict__ arena, int32_t base, int32_t n, int32_t* __restrict__ out) {
+  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+    out[v] = arena[base + v] - base;
+}
+
+// Check a graph-local image before it is placed: every entry in range and
+// pointing from lower to strictly higher priority (then no cycle); count the
+// roots.  res[0] = bad entries, res[1] = roots.
+template <bool HASH>
+__global__ void k_check_image(const int32_t* __restrict__ img, int32_t n, unsigned long long* __restrict__ res) {
+  unsigned long long bad = 0, roots = 0;
+  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+    const int32_t q = img[v];
+    if (q < 0 || q >= n) {
+      ++bad;
+    } else if (q == v) {
+      ++roots;
+    } else if (HASH ? !(fmix32((uint32_t)q) < fmix32((uint32_t)v)) : !(q < v)) {
+      ++bad;
+    }
+  }
+  bad = (unsigned long long)wave_sum((int)bad);
+  roots = (unsigned long long)wave_sum((int)roots);
+  if ((threadIdx.x & 63) == 0) {
+    if (bad) atomicAdd(res, bad);
+    if (roots) atomicAdd(res + 1, roots);
+  }
+}
+
+__global__ void k_place(const int32_t* __restrict__ img, int32_t base, int32_t n, int32_t* __restrict__ arena) {
+  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+    arena[base + v] = img[v] + base;
+}
+
 }  // namespace
 }  // namespace ccdev

@@ -68,17 +68,24 @@ class Scheduler:
         self.evictions = 0
         self.admissions = 0
 
-    def _make_room(self, s):
-        """Make stream s resident, evicting idle least-recently-used streams
-        if the budget requires it.  Returns False if it cannot right now."""
+    def _make_room(self, s, allow_waiting_victims):
+        """Make stream s resident.  Idle streams are evicted to make room:
+        first those with no queued work, least recently used first; streams
+        that still have queued requests only if `allow_waiting_victims`.
+        Returns False if it cannot right now (nothing is changed then)."""
         if self.ex.resident(s):
             return True
         need = self.sizes[s]
-        while not self.ex.can_admit(need):
-            idle = [t for t in self.ex.resident_streams() if t not in self.busy and t != s]
+        idle = [t for t in self.ex.resident_streams() if t not in self.busy and t != s]
+        idle.sort(key=lambda t: (len(self.fifo[t]) > 0, self.last_use.get(t, -1)))
+        if not allow_waiting_victims:
+            idle = [t for t in idle if not self.fifo[t]]
+        plan = []
+        while not self.ex.can_admit_after(need, plan):
             if not idle:
                 return False
-            victim = min(idle, key=lambda t: self.last_use.get(t, -1))
+            plan.append(idle.pop(0))
+        for victim in plan:
             self.ex.evict(victim)
             self.evictions += 1
         self.ex.admit(s, need)
@@ -101,7 +108,8 @@ class Scheduler:
         ready = [s for s, q in self.fifo.items() if q and s not in self.busy]
         if not ready:
             return False
-        ready.sort(key=lambda s: self.fifo[s][0].arrival)  # oldest head first
+        # resident streams first (no transfer), each group oldest head first
+        ready.sort(key=lambda s: (not self.ex.resident(s), self.fifo[s][0].arrival))
         picked, items = [], 0
         for s in ready:
             if len(picked) >= self.max_reqs:
@@ -109,7 +117,8 @@ class Scheduler:
             r = self.fifo[s][0]
             if picked and items + r.size > self.max_items:
                 continue
-            if not self._make_room(s):
+            # evicting a stream that has queued work only pays when nothing else can run
+            if not self._make_room(s, allow_waiting_victims=not picked and not self.inflight):
                 continue
             self.fifo[s].popleft()
             picked.append(r)
@@ -146,10 +155,31 @@ class Scheduler:
         return reqs
 
 
-def serial_scheduler(executor, stream_sizes):
+class SerialScheduler(Scheduler):
     """The plain baseline: one request per launch, one launch at a time, in
     arrival order (a FIFO in front of a serial server)."""
-    return Scheduler(executor, stream_sizes, max_inflight=1, max_requests_per_round=1)
+
+    def __init__(self, executor, stream_sizes):
+        super().__init__(executor, stream_sizes, max_inflight=1, max_requests_per_round=1)
+
+    def _launch_round(self):
+        ready = [s for s, q in self.fifo.items() if q and s not in self.busy]
+        if not ready:
+            return False
+        s = min(ready, key=lambda t: self.fifo[t][0].arrival)
+        if not self._make_room(s, allow_waiting_victims=True):
+            return False
+        r = self.fifo[s].popleft()
+        self.busy.add(s)
+        self.last_use[s] = self.rounds
+        self.inflight.append((self.ex.launch([(r.stream, r.kind, r.items, r.out)]), [r]))
+        self.rounds += 1
+        self.round_sizes.append(1)
+        return True
+
+
+def serial_scheduler(executor, stream_sizes):
+    return SerialScheduler(executor, stream_sizes)
 
 
 class GpuExecutor:
@@ -183,6 +213,13 @@ class GpuExecutor:
 
     def can_admit(self, n):
         return self.pool.largest_gap() >= n
+
+    def can_admit_after(self, n, victims):
+        """Would a graph of n vertices fit once `victims` are evicted?"""
+        if not victims:
+            return self.can_admit(n)
+        gaps = self.pool.gaps_after_removing([self.gid[v] for v in victims])
+        return max(gaps, default=0) >= n
 
     def admit(self, s, n):
         # the entries taken belonged to graphs with no work left in flight

@@ -42,6 +42,9 @@ class OracleExecutor:
     def can_admit(self, n):
         return self.used + n <= self.budget
 
+    def can_admit_after(self, n, victims):
+        return self.used - sum(self.nsize[v] for v in victims) + n <= self.budget
+
     def admit(self, s, n):
         assert self.can_admit(n)
         self.used += n

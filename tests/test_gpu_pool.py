@@ -117,6 +117,14 @@ def test_pool_gaps_eviction_and_images(cc):
     pool.load(b2, img)
     np.testing.assert_array_equal(pool.labels(b2).cpu().numpy(), ref.labels())
     assert pool.num_components(b2) == ref.num_components()
+    # a corrupt image is refused on the device and the graph is left as it was
+    bad = bytearray(img)
+    par = np.frombuffer(bad, np.int32, offset=16)
+    par[10] = 11  # points upward in id order
+    with pytest.raises(cc.CCError) as ei:
+        pool.load(b2, bad)
+    assert ei.value.code == cc.cc.CC_ECORRUPT
+    np.testing.assert_array_equal(pool.labels(b2).cpu().numpy(), ref.labels())
     # the image is a cc_save image: a standalone graph takes it as is
     g = cc.Graph(3000)
     g.load(img)

@@ -28,7 +28,10 @@ def run_stream(cc, s, opts, max_items=None):
     qo = torch.from_numpy(s.qoff.astype(np.int64)).cuda()
     out = torch.full((len(s.queries),), 7, dtype=torch.uint8, device="cuda")
     g.bulk_stream(E, eo, Q, qo, out, max_items=max_items)
-    rc = g.sync()
+    try:
+        rc = g.sync()
+    except cc.CCError as e:  # a device error (the barrier timeout) raises
+        rc = e.code
     return g, out.cpu().numpy(), rc
 
 
