@@ -40,8 +40,11 @@ struct BulkFindScratch {
                       // [5..7] Phase II change flags (ring), [8..10] barrier
 };
 
+// First visit of v?  A plain read skips the atomic for vertices already seen
+// (hub vertices appear in many edges); the atomic decides the rest.
 __device__ __forceinline__ bool test_and_set(uint32_t* bits, int32_t v) {
   const uint32_t m = 1u << (v & 31);
+  if (ld((const int32_t*)bits + (v >> 5)) & (int32_t)m) return false;
   return (atomicOr(bits + (v >> 5), m) & m) == 0u;
 }
 

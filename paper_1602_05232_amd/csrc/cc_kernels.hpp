@@ -302,7 +302,10 @@ __global__ void k_labels_min(int32_t* __restrict__ parent, int32_t n, int32_t* _
   for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
     const int32_t r = find_halve<R>(parent, v, n, flags);
     if (r != v && ld(parent + v) != r) st(parent + v, r);
-    atomicMin(out + r, v);
+    // a big component's root slot is hit by millions of vertices: read it
+    // first and only try the atomic while it may still go down (blocks run
+    // roughly in id order, so the minimum arrives early)
+    if (ld(out + r) > v) atomicMin(out + r, v);
   }
 }
 

@@ -144,7 +144,7 @@ __global__ void k_pool_labels_min(int32_t* __restrict__ arena, int32_t base, int
   for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
     const int32_t r = find_halve(arena, base + v, n, flags);
     if (ld(arena + base + v) != r) st(arena + base + v, r);
-    atomicMin(out + (r - base), v);
+    if (ld(out + (r - base)) > v) atomicMin(out + (r - base), v);  // see k_labels_min
   }
 }
 
