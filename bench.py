@@ -46,8 +46,8 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# sources of the plain update kernels: a change to any of them voids stored counter readings
-KERNEL_SOURCES = ("uf_device.hpp", "cc_kernels.hpp", "cc_plain.hip", "cc_internal.hpp")
+# sources of the update kernel: a change to either voids stored counter readings
+KERNEL_SOURCES = ("uf_device.hpp", "cc_kernels.hpp")
 
 
 def source_digest() -> str:

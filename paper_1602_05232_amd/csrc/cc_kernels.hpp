@@ -13,9 +13,8 @@
 //                    path compression of Section 6.1, applied to the roots the
 //                    minibatch touched)
 //   k_query          Algorithm 1: out[i] = find(u_i) == find(v_i)
-//   k_labels_*       min-id component labels
-//   k_compress_all   every vertex points at its root
-//   k_count_roots    number of v with parent[v] == v
+// (passes over all vertices -- labels, compression, root count -- are in
+// cc_vertex_kernels.hpp)
 #pragma once
 
 #include "uf_device.hpp"
@@ -276,72 +275,6 @@ __global__ void k_query(int32_t* __restrict__ parent, const int2* __restrict__ p
       }
       if (i < q) out[i] = a;
     }
-  }
-}
-
-// Id order: every root is its tree's smallest id, so the label is the root.
-// Each vertex is also pointed straight at its root.
-__global__ void k_labels_id(int32_t* __restrict__ parent, int32_t n, int32_t* __restrict__ out,
-                            int* __restrict__ flags) {
-  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
-    const int32_t r = find_halve(parent, v, n, flags);
-    if (ld(parent + v) != r) st(parent + v, r);
-    out[v] = r;
-  }
-}
-
-__global__ void k_fill_i32(int32_t* __restrict__ out, int32_t n, int32_t value) {
-  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) out[v] = value;
-}
-
-// Hashed order, pass 1: the minimum id of each tree collects in its root's slot
-// (out pre-filled with n).
-template <bool R = false>
-__global__ void k_labels_min(int32_t* __restrict__ parent, int32_t n, int32_t* __restrict__ out,
-                             int* __restrict__ flags) {
-  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
-    const int32_t r = find_halve<R>(parent, v, n, flags);
-    if (r != v && ld(parent + v) != r) st(parent + v, r);
-    // a big component's root slot is hit by millions of vertices: read it
-    // first and only try the atomic while it may still go down (blocks run
-    // roughly in id order, so the minimum arrives early)
-    if (ld(out + r) > v) atomicMin(out + r, v);
-  }
-}
-
-// Hashed order, pass 2: every vertex copies its root's minimum.  A root
-// rewrites its own slot with the same value; non-root slots are never read.
-template <bool R = false>
-__global__ void k_labels_gather(const int32_t* __restrict__ parent, int32_t n, int32_t* __restrict__ out,
-                                int* __restrict__ flags) {
-  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
-    const int32_t r = find_read<R>(parent, v, n, flags);
-    out[v] = out[r];
-  }
-}
-
-template <bool R = false>
-__global__ void k_compress_all(int32_t* __restrict__ parent, int32_t n, int* __restrict__ flags) {
-  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
-    const int32_t r = find_halve<R>(parent, v, n, flags);
-    if (r != v && ld(parent + v) != r) st(parent + v, r);
-  }
-}
-
-template <bool R = false>
-__global__ void k_count_roots(const int32_t* __restrict__ parent, int32_t n,
-                              unsigned long long* __restrict__ result) {
-  __shared__ int part[16];
-  int c = 0;
-  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
-    c += pid<R>(parent[v]) == v;
-  c = wave_sum(c);
-  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned long long s = 0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += part[w];
-    if (s) atomicAdd(result, s);
   }
 }
 

@@ -12,6 +12,7 @@
 #include "../../include/cc.h"
 #include "cc_internal.hpp"
 #include "cc_kernels.hpp"
+#include "cc_vertex_kernels.hpp"
 #include "cc_bulkfind_kernels.hpp"
 #include "cc_stream_kernels.hpp"
 
@@ -446,12 +447,12 @@ extern "C" int cc_labels(cc_graph* g, int32_t* out) {
   const unsigned blocks = vertex_blocks(g);
   const int32_t n = (int32_t)g->n;
   if (g->tune.hook == 1) {
-    hipLaunchKernelGGL(k_fill_i32, dim3(blocks), dim3(256), 0, g->stream, out, n, n);
+    hipLaunchKernelGGL(k_iota_i32, dim3(blocks), dim3(256), 0, g->stream, out, n);
     hipLaunchKernelGGL(k_labels_min<false>, dim3(blocks), dim3(256), 0, g->stream, g->parent, n, out, g->flags);
     hipLaunchKernelGGL(k_labels_gather<false>, dim3(blocks), dim3(256), 0, g->stream, g->parent, n, out,
                        g->flags);
   } else if (g->tune.hook == 2) {
-    hipLaunchKernelGGL(k_fill_i32, dim3(blocks), dim3(256), 0, g->stream, out, n, n);
+    hipLaunchKernelGGL(k_iota_i32, dim3(blocks), dim3(256), 0, g->stream, out, n);
     hipLaunchKernelGGL(k_labels_min<true>, dim3(blocks), dim3(256), 0, g->stream, g->parent, n, out, g->flags);
     hipLaunchKernelGGL(k_labels_gather<true>, dim3(blocks), dim3(256), 0, g->stream, g->parent, n, out,
                        g->flags);

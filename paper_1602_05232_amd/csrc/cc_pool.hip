@@ -426,7 +426,7 @@ extern "C" int cc_pool_labels(cc_pool* p, int32_t id, int32_t* out) {
   const unsigned blocks = blocks_for(g.n, 256, 4096);
   const int32_t base = (int32_t)g.base, n = (int32_t)g.n;
   if (p->tune.hook == 1) {
-    hipLaunchKernelGGL(k_fill_i32, dim3(blocks), dim3(256), 0, p->stream, out, n, n);
+    hipLaunchKernelGGL(k_iota_i32, dim3(blocks), dim3(256), 0, p->stream, out, n);
     hipLaunchKernelGGL(k_pool_labels_min, dim3(blocks), dim3(256), 0, p->stream, p->arena, base, n, out, p->flags);
     hipLaunchKernelGGL(k_pool_labels_gather, dim3(blocks), dim3(256), 0, p->stream, p->arena, base, n, out,
                        p->flags);

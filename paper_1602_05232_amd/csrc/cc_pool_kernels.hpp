@@ -11,6 +11,7 @@
 #pragma once
 
 #include "cc_kernels.hpp"
+#include "cc_vertex_kernels.hpp"
 
 namespace ccdev {
 namespace {  // kernels get internal linkage in every translation unit
@@ -138,11 +139,13 @@ __global__ void k_pool_labels_id(int32_t* __restrict__ arena, int32_t base, int3
   }
 }
 
-// Hashed order: minimum id per root (out pre-filled with n), then a gather.
+// Hashed order: minimum id per root (out pre-filled with out[v] = v, so a
+// root needs no atomic), then a gather.
 __global__ void k_pool_labels_min(int32_t* __restrict__ arena, int32_t base, int32_t n, int32_t* __restrict__ out,
                                   int* __restrict__ flags) {
   for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
     const int32_t r = find_halve(arena, base + v, n, flags);
+    if (r == base + v) continue;
     if (ld(arena + base + v) != r) st(arena + base + v, r);
     if (ld(out + (r - base)) > v) atomicMin(out + (r - base), v);  // see k_labels_min
   }
