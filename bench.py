@@ -194,8 +194,11 @@ def run_rmat(args):
         fused = opts.get("update_mode", 0) == 0
         tag = ("update_fused_rmat%d" if fused else "update_split_rmat%d") % args.scale
         achieved = UPDATE_BYTES_PER_EDGE * upd_rate / 1e9
+        traffic = load_traffic(tag)
         res["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic(tag),
+                           "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                           "traffic_rate_GBs": None if traffic is None else
+                           traffic * nb * steps / sum(upd_t) / 1e9,
                            "kernel": "k_update_fused" if fused else "k_filter+k_link_live+k_compress_live",
                            "bytes_per_edge": UPDATE_BYTES_PER_EDGE,
                            "avg_update_ms": sum(upd_t) / (steps * nb) * 1e3,
@@ -383,6 +386,19 @@ def run_batched(args):
     wall_plain = timed(plain_step, "per-graph")
     wall_pool = timed(pool_step, "pool")
     assert torch.equal(out, out_plain), "pool answers differ from per-graph answers"
+    # the same run with all rounds of a step in one cooperative launch
+    ops_all = [op for ops in ops_per_step for op in ops]
+    pool.set_option("one_launch", 1)
+
+    def pool_one_launch():
+        pool.reset_all()
+        pool.run(ops_all)
+        return pool.sync()
+
+    out.zero_()
+    wall_one = timed(pool_one_launch, "pool-one-launch")
+    assert torch.equal(out, out_plain), "one-launch pool answers differ from per-graph answers"
+    pool.set_option("one_launch", 0)
     comps = sum(pool.num_components(i) for i in ids)
     assert comps == sum(gr.num_components() for gr in graphs)
     for gr in graphs:
@@ -394,7 +410,10 @@ def run_batched(args):
         "edges": M, "queries": Qn, "steps_per_graph": 4, "queries_per_step": 1 << 12,
         "n_distribution": "clip(round(2^X), 2^10, 2^20), X ~ N(14, 2)", "form": "pool", "options": popts})
     res.update({"plain_value": steps * (M + Qn) / wall_plain, "plain_ms_per_step": wall_plain / steps * 1e3,
-                "speedup_vs_plain": wall_plain / wall_pool, "components": comps})
+                "speedup_vs_plain": wall_plain / wall_pool, "components": comps,
+                "one_launch": {"value": steps * (M + Qn) / wall_one, "ms_per_step": wall_one / steps * 1e3,
+                               "speedup_vs_plain": wall_plain / wall_one,
+                               "what": "all 8 rounds of a step in one cooperative launch"}})
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(streams, args.cpu_budget)
     return res

@@ -89,7 +89,11 @@ enum cc_option {
    * that meet are merged, and every traversed vertex is pointed at its root;
    * one cooperative launch per bulk operation, about 12 bytes of scratch per
    * vertex, not available during capture. */
-  CC_OPT_FIND = 10
+  CC_OPT_FIND = 10,
+  /* Pools only (cc_pool_run): 1 = all rounds of a run in one cooperative
+   * launch, separated by device-wide barriers, instead of one launch per
+   * round; no linked-root compression in that form.  Default 0. */
+  CC_OPT_ONE_LAUNCH = 11
 };
 
 /* Create a graph on vertices [0, n), 1 <= n <= 2^31 - 1, every vertex its own

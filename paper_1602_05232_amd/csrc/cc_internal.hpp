@@ -53,6 +53,7 @@ struct Tuning {
   int compress_linked = 1;  // CC_OPT_COMPRESS_LINKED
   int64_t spin_limit = 1 << 24;  // CC_OPT_SPIN_LIMIT
   int find = 0;                  // CC_OPT_FIND
+  int one_launch = 0;            // CC_OPT_ONE_LAUNCH (pools)
 };
 
 inline bool set_tuning(Tuning* t, int key, int64_t v) {
@@ -97,6 +98,10 @@ inline bool set_tuning(Tuning* t, int key, int64_t v) {
       if (v != 0 && v != 1) return false;
       t->find = (int)v;
       return true;
+    case CC_OPT_ONE_LAUNCH:
+      if (v != 0 && v != 1) return false;
+      t->one_launch = (int)v;
+      return true;
     default:
       return false;
   }
@@ -114,6 +119,7 @@ inline bool get_tuning(const Tuning* t, int key, int64_t* v) {
     case CC_OPT_COMPRESS_LINKED: *v = t->compress_linked; return true;
     case CC_OPT_SPIN_LIMIT: *v = t->spin_limit; return true;
     case CC_OPT_FIND: *v = t->find; return true;
+    case CC_OPT_ONE_LAUNCH: *v = t->one_launch; return true;
     default: return false;
   }
 }

@@ -330,6 +330,10 @@ extern "C" int cc_set_stream(cc_graph* g, void* stream) {
 
 extern "C" int cc_set_option(cc_graph* g, int key, int64_t value) {
   if (!g) return CC_EINVAL;
+  if (key == CC_OPT_ONE_LAUNCH) {
+    cc_set_error("cc_set_option: CC_OPT_ONE_LAUNCH applies to pools only");
+    return CC_EINVAL;
+  }
   if (key == CC_OPT_HOOK && value == 2 && g->n > (int64_t)kIdMask + 1) {
     cc_set_error("cc_set_option: union by rank needs n <= 2^%d", kRankShift);
     return CC_EINVAL;

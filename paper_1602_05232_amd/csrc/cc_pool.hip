@@ -35,6 +35,9 @@ struct RingSlot {
   int64_t cap = 0;
   int32_t* hooked = nullptr;  // capacity entries, allocated on first use
   unsigned* ctl = nullptr;    // [0] hooked count, [1] finished blocks
+  int32_t* meta_host = nullptr;  // one-launch form: round starts, then round tiles
+  int32_t* meta_dev = nullptr;
+  int64_t meta_cap = 0;
   hipEvent_t done = nullptr;
   bool pending = false;
 };
@@ -54,6 +57,7 @@ struct cc_pool {
   int32_t* staging = nullptr;       // device image buffer for save / load
   int64_t staging_cap = 0;
   unsigned long long* check = nullptr;  // [0] bad entries, [1] roots (image check)
+  unsigned* bar = nullptr;              // device-wide barrier of the one-launch form
   RingSlot ring[kRing];
   int ring_next = 0;
   cc::Tuning tune;
@@ -126,6 +130,65 @@ int reserve_slot(cc_pool* p, int64_t count, bool record, RingSlot** out) {
   return CC_OK;
 }
 
+int reserve_meta(RingSlot* s, int64_t words) {
+  if (s->meta_cap >= words) return CC_OK;
+  if (s->meta_host) (void)hipHostFree(s->meta_host);
+  if (s->meta_dev) (void)hipFree(s->meta_dev);
+  s->meta_host = nullptr;
+  s->meta_dev = nullptr;
+  s->meta_cap = 0;
+  const int64_t cap = std::max<int64_t>(words, 256);
+  if (hipHostMalloc((void**)&s->meta_host, (size_t)cap * 4, hipHostMallocDefault) != hipSuccess ||
+      hipMalloc((void**)&s->meta_dev, (size_t)cap * 4) != hipSuccess) {
+    cc_set_error("cc_pool_run: round table allocation failed");
+    return CC_ENOMEM;
+  }
+  s->meta_cap = cap;
+  return CC_OK;
+}
+
+template <int ITEMS, bool HASH, bool HALVE>
+int launch_rounds_t(cc_pool* p, const RingSlot* s, int rounds, uint32_t max_tiles) {
+  const int B = p->tune.block;
+  int per_cu = 0, cus = 0;
+  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pool_rounds<ITEMS, HASH, HALVE>, B, 0));
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device));
+  int64_t grid = std::min<int64_t>(std::min<int64_t>(max_tiles, (int64_t)per_cu * cus), p->tune.grid_cap);
+  grid = std::max<int64_t>(grid, 1);
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, p->stream, p->bar, 3);
+  HIP_TRY(hipGetLastError());
+  const OpDesc* ops = s->dev;
+  const int32_t* rstart = s->meta_dev;
+  const uint32_t* rtiles = reinterpret_cast<const uint32_t*>(s->meta_dev + rounds + 1);
+  int32_t* arena = p->arena;
+  unsigned long long* glinks = p->glinks;
+  int* flags = p->flags;
+  unsigned* bar = p->bar;
+  unsigned spin = (unsigned)p->tune.spin_limit;
+  void* args[] = {&ops, &rstart, &rtiles, &rounds, &arena, &glinks, &flags, &bar, &spin};
+  HIP_TRY(hipLaunchCooperativeKernel((const void*)k_pool_rounds<ITEMS, HASH, HALVE>, dim3((unsigned)grid), dim3(B),
+                                     args, 0, p->stream));
+  return CC_OK;
+}
+
+template <int ITEMS>
+int launch_rounds_i(cc_pool* p, const RingSlot* s, int rounds, uint32_t max_tiles) {
+  const bool hash = p->tune.hook == 1, halve = p->tune.query_halving != 0;
+  if (hash) return halve ? launch_rounds_t<ITEMS, true, true>(p, s, rounds, max_tiles)
+                         : launch_rounds_t<ITEMS, true, false>(p, s, rounds, max_tiles);
+  return halve ? launch_rounds_t<ITEMS, false, true>(p, s, rounds, max_tiles)
+               : launch_rounds_t<ITEMS, false, false>(p, s, rounds, max_tiles);
+}
+
+int launch_rounds(cc_pool* p, const RingSlot* s, int items, int rounds, uint32_t max_tiles) {
+  switch (items) {
+    case 1: return launch_rounds_i<1>(p, s, rounds, max_tiles);
+    case 2: return launch_rounds_i<2>(p, s, rounds, max_tiles);
+    case 8: return launch_rounds_i<8>(p, s, rounds, max_tiles);
+    default: return launch_rounds_i<4>(p, s, rounds, max_tiles);
+  }
+}
+
 template <int ITEMS, bool HASH, bool RECORD>
 void launch_phase_t(cc_pool* p, const RingSlot* s, const OpDesc* d, int nops, uint32_t ntiles) {
   const int B = p->tune.block;
@@ -185,6 +248,7 @@ extern "C" cc_pool* cc_pool_create(int64_t capacity, int32_t max_graphs) {
   if (hipMalloc(&p->arena, (size_t)capacity * 4) != hipSuccess) return fail("arena");
   if (hipMalloc(&p->glinks, (size_t)max_graphs * kPoolLinkStride * 8) != hipSuccess) return fail("links");
   if (hipMalloc(&p->flags, 64) != hipSuccess) return fail("flags");
+  if (hipMalloc(&p->bar, 64) != hipSuccess) return fail("bar");
   if (hipMemsetAsync(p->flags, 0, 64, p->stream) != hipSuccess) return fail("memset");
   if (hipMemsetAsync(p->glinks, 0, (size_t)max_graphs * kPoolLinkStride * 8, p->stream) != hipSuccess)
     return fail("memset");
@@ -204,6 +268,8 @@ extern "C" int cc_pool_destroy(cc_pool* p) {
     if (s.dev) (void)hipFree(s.dev);
     if (s.hooked) (void)hipFree(s.hooked);
     if (s.ctl) (void)hipFree(s.ctl);
+    if (s.meta_host) (void)hipHostFree(s.meta_host);
+    if (s.meta_dev) (void)hipFree(s.meta_dev);
     if (s.done) (void)hipEventDestroy(s.done);
   }
   (void)hipFree(p->arena);
@@ -211,6 +277,7 @@ extern "C" int cc_pool_destroy(cc_pool* p) {
   (void)hipFree(p->flags);
   (void)hipFree(p->staging);
   (void)hipFree(p->check);
+  (void)hipFree(p->bar);
   delete p;
   return CC_OK;
 }
@@ -223,7 +290,7 @@ extern "C" int cc_pool_set_stream(cc_pool* p, void* stream) {
 
 extern "C" int cc_pool_set_option(cc_pool* p, int key, int64_t value) {
   if (!p) return CC_EINVAL;
-  if (key == CC_OPT_UPDATE_MODE || key == CC_OPT_COMPRESS_EVERY) {
+  if (key == CC_OPT_UPDATE_MODE || key == CC_OPT_COMPRESS_EVERY || key == CC_OPT_FIND) {
     cc_set_error("cc_pool_set_option: option %d does not apply to pools", key);
     return CC_EINVAL;
   }
@@ -361,8 +428,9 @@ extern "C" int cc_pool_run(cc_pool* p, const cc_op* ops, int32_t num_ops) {
   DeviceGuard dg(p->device);
   bool any_update = false;
   for (int32_t i = 0; i < num_ops; ++i) any_update |= ops[i].kind == 0 && ops[i].count > 0;
+  const bool one_launch = p->tune.one_launch != 0;
   RingSlot* slot = nullptr;
-  int rc = reserve_slot(p, live, any_update && p->tune.compress_linked, &slot);
+  int rc = reserve_slot(p, live, any_update && p->tune.compress_linked && !one_launch, &slot);
   if (rc != CC_OK) return rc;
   const int B = p->tune.block;
   // lay the descriptors out round by round; each round gets its own items per thread
@@ -379,7 +447,10 @@ extern "C" int cc_pool_run(cc_pool* p, const cc_op* ops, int32_t num_ops) {
   std::vector<int64_t> fill(rstart.begin(), rstart.end() - 1);
   std::vector<int> ritem_per_thread((size_t)rounds);
   std::vector<uint32_t> rtiles((size_t)rounds, 0);
-  for (int r = 0; r < rounds; ++r) ritem_per_thread[(size_t)r] = cc::pick_items(p->tune.items, ritems[(size_t)r], B);
+  int64_t max_round_items = 0;
+  for (int r = 0; r < rounds; ++r) max_round_items = std::max(max_round_items, ritems[(size_t)r]);
+  for (int r = 0; r < rounds; ++r)
+    ritem_per_thread[(size_t)r] = cc::pick_items(p->tune.items, one_launch ? max_round_items : ritems[(size_t)r], B);
   for (int32_t i = 0; i < num_ops; ++i) {
     const cc_op& o = ops[i];
     if (o.count == 0) continue;
@@ -404,6 +475,29 @@ extern "C" int cc_pool_run(cc_pool* p, const cc_op* ops, int32_t num_ops) {
     rtiles[(size_t)r] += (uint32_t)nt;
   }
   HIP_TRY(hipMemcpyAsync(slot->dev, slot->host, (size_t)live * sizeof(OpDesc), hipMemcpyHostToDevice, p->stream));
+  if (one_launch) {
+    // compact the non-empty rounds into the round table: starts, then tiles
+    std::vector<int> used;
+    for (int r = 0; r < rounds; ++r)
+      if (rcount[(size_t)r] > 0) used.push_back(r);
+    const int nr = (int)used.size();
+    rc = reserve_meta(slot, 2 * (int64_t)nr + 1);
+    if (rc != CC_OK) return rc;
+    uint32_t max_tiles = 1;
+    for (int k = 0; k < nr; ++k) {
+      slot->meta_host[k] = (int32_t)rstart[(size_t)used[(size_t)k]];
+      slot->meta_host[nr + 1 + k] = (int32_t)rtiles[(size_t)used[(size_t)k]];
+      max_tiles = std::max(max_tiles, rtiles[(size_t)used[(size_t)k]]);
+    }
+    slot->meta_host[nr] = (int32_t)(rstart[(size_t)used[(size_t)nr - 1]] + rcount[(size_t)used[(size_t)nr - 1]]);
+    HIP_TRY(hipMemcpyAsync(slot->meta_dev, slot->meta_host, (size_t)(2 * nr + 1) * 4, hipMemcpyHostToDevice,
+                           p->stream));
+    rc = launch_rounds(p, slot, ritem_per_thread[0], nr, max_tiles);
+    if (rc != CC_OK) return rc;
+    HIP_TRY(hipEventRecord(slot->done, p->stream));
+    slot->pending = true;
+    return CC_OK;
+  }
   for (int r = 0; r < rounds; ++r) {
     if (rcount[(size_t)r] == 0) continue;
     const bool record = rupd[(size_t)r] && p->tune.compress_linked;

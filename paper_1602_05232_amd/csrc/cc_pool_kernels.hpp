@@ -11,6 +11,7 @@
 #pragma once
 
 #include "cc_kernels.hpp"
+#include "cc_stream_kernels.hpp"
 #include "cc_vertex_kernels.hpp"
 
 namespace ccdev {
@@ -50,6 +51,75 @@ __device__ __forceinline__ int block_sum(int v, int* red) {
   return s;  // valid in thread 0
 }
 
+// One tile of one operation (block-uniform: every thread of the block calls it).
+template <int ITEMS, bool HASH, bool RECORD, bool HALVE_Q>
+__device__ __forceinline__ void pool_tile(const OpDesc& op, uint32_t t, int32_t* __restrict__ arena,
+                                          unsigned long long* __restrict__ glinks, int* __restrict__ flags,
+                                          int32_t* __restrict__ hooked, unsigned* __restrict__ hooked_ctl,
+                                          int* wave_off, unsigned* blk, int* red) {
+  const uint32_t T = blockDim.x * ITEMS;
+  const int64_t t0 = (int64_t)(t - op.tile0) * T;
+  int2 e[ITEMS];
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) {
+    const int64_t i = t0 + (int64_t)k * blockDim.x + threadIdx.x;
+    e[k] = i < op.count ? op.items[i] : make_int2(0, 0);
+  }
+  if (op.kind == 0) {
+    int32_t hk[ITEMS];
+    int nh = 0;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      hk[k] = -1;
+      if (!in_range(e[k], op.n)) {
+        raise_flag(flags, kFlagRange);
+        continue;
+      }
+      if (e[k].x == e[k].y) continue;
+      const int32_t u = op.base + e[k].x, v = op.base + e[k].y;
+      const int32_t pu = ld(arena + u), pv = ld(arena + v);
+      if (pu == pv || pu == v || pv == u) continue;
+      const int32_t ru = find_halve_from(arena, u, pu, op.n, flags);
+      const int32_t rv = find_halve_from(arena, v, pv, op.n, flags);
+      if (ru != rv) {
+        if (HASH) {
+          ByHash o;
+          o.base = op.base;
+          hk[k] = link_roots(arena, ru, rv, op.n, flags, o);
+        } else {
+          hk[k] = link_roots(arena, ru, rv, op.n, flags, ById{});
+        }
+        if (hk[k] >= 0) ++nh;
+      }
+    }
+    const int links = block_sum(nh, red);
+    if (threadIdx.x == 0 && links > 0)
+      atomicAdd(glinks + (size_t)op.graph * kPoolLinkStride, (unsigned long long)links);
+    if (RECORD) {
+      unsigned pos = block_reserve(nh, hooked_ctl, wave_off, blk);
+#pragma unroll
+      for (int k = 0; k < ITEMS; ++k)
+        if (hk[k] >= 0) hooked[pos++] = hk[k];
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      const int64_t i = t0 + (int64_t)k * blockDim.x + threadIdx.x;
+      uint8_t a = 0;
+      if (!in_range(e[k], op.n)) {
+        raise_flag(flags, kFlagRange);
+      } else if (e[k].x == e[k].y) {
+        a = 1;
+      } else {
+        const int32_t ru = find_root<HALVE_Q>(arena, op.base + e[k].x, op.n, flags);
+        const int32_t rv = find_root<HALVE_Q>(arena, op.base + e[k].y, op.n, flags);
+        a = ru == rv;
+      }
+      if (i < op.count) op.out[i] = a;
+    }
+  }
+}
+
 template <int ITEMS, bool HASH, bool RECORD, bool HALVE_Q>
 __global__ void k_pool_phase(const OpDesc* __restrict__ ops, int nops, uint32_t ntiles,
                              int32_t* __restrict__ arena, unsigned long long* __restrict__ glinks,
@@ -58,69 +128,34 @@ __global__ void k_pool_phase(const OpDesc* __restrict__ ops, int nops, uint32_t 
   __shared__ int wave_off[16];
   __shared__ unsigned blk[2];
   __shared__ int red[16];
-  const uint32_t T = blockDim.x * ITEMS;
   for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const OpDesc op = ops[find_op(ops, nops, t)];
-    const int64_t t0 = (int64_t)(t - op.tile0) * T;
-    int2 e[ITEMS];
-#pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-      const int64_t i = t0 + (int64_t)k * blockDim.x + threadIdx.x;
-      e[k] = i < op.count ? op.items[i] : make_int2(0, 0);
+    pool_tile<ITEMS, HASH, RECORD, HALVE_Q>(op, t, arena, glinks, flags, hooked, hooked_ctl, wave_off, blk, red);
+  }
+}
+
+// Every round of a run in one cooperative launch: round r covers descriptors
+// [rstart[r], rstart[r+1]) and rtiles[r] tiles; device-wide barriers keep the
+// rounds in order (an operation of round r+1 may depend on one of round r on
+// the same graph).  No linked-root recording in this form.
+template <int ITEMS, bool HASH, bool HALVE_Q>
+__global__ void k_pool_rounds(const OpDesc* __restrict__ ops, const int32_t* __restrict__ rstart,
+                              const uint32_t* __restrict__ rtiles, int nrounds, int32_t* __restrict__ arena,
+                              unsigned long long* __restrict__ glinks, int* __restrict__ flags, unsigned* bar,
+                              unsigned spin_limit) {
+  __shared__ int wave_off[16];
+  __shared__ unsigned blk[2];
+  __shared__ int red[16];
+  unsigned gen = 0;
+  for (int r = 0; r < nrounds; ++r) {
+    const OpDesc* ro = ops + rstart[r];
+    const int nops = rstart[r + 1] - rstart[r];
+    const uint32_t ntiles = rtiles[r];
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+      const OpDesc op = ro[find_op(ro, nops, t)];
+      pool_tile<ITEMS, HASH, false, HALVE_Q>(op, t, arena, glinks, flags, nullptr, nullptr, wave_off, blk, red);
     }
-    if (op.kind == 0) {
-      int32_t hk[ITEMS];
-      int nh = 0;
-#pragma unroll
-      for (int k = 0; k < ITEMS; ++k) {
-        hk[k] = -1;
-        if (!in_range(e[k], op.n)) {
-          raise_flag(flags, kFlagRange);
-          continue;
-        }
-        if (e[k].x == e[k].y) continue;
-        const int32_t u = op.base + e[k].x, v = op.base + e[k].y;
-        const int32_t pu = ld(arena + u), pv = ld(arena + v);
-        if (pu == pv || pu == v || pv == u) continue;
-        const int32_t ru = find_halve_from(arena, u, pu, op.n, flags);
-        const int32_t rv = find_halve_from(arena, v, pv, op.n, flags);
-        if (ru != rv) {
-          if (HASH) {
-            ByHash o;
-            o.base = op.base;
-            hk[k] = link_roots(arena, ru, rv, op.n, flags, o);
-          } else {
-            hk[k] = link_roots(arena, ru, rv, op.n, flags, ById{});
-          }
-          if (hk[k] >= 0) ++nh;
-        }
-      }
-      const int links = block_sum(nh, red);
-      if (threadIdx.x == 0 && links > 0)
-        atomicAdd(glinks + (size_t)op.graph * kPoolLinkStride, (unsigned long long)links);
-      if (RECORD) {
-        unsigned pos = block_reserve(nh, hooked_ctl, wave_off, blk);
-#pragma unroll
-        for (int k = 0; k < ITEMS; ++k)
-          if (hk[k] >= 0) hooked[pos++] = hk[k];
-      }
-    } else {
-#pragma unroll
-      for (int k = 0; k < ITEMS; ++k) {
-        const int64_t i = t0 + (int64_t)k * blockDim.x + threadIdx.x;
-        uint8_t a = 0;
-        if (!in_range(e[k], op.n)) {
-          raise_flag(flags, kFlagRange);
-        } else if (e[k].x == e[k].y) {
-          a = 1;
-        } else {
-          const int32_t ru = find_root<HALVE_Q>(arena, op.base + e[k].x, op.n, flags);
-          const int32_t rv = find_root<HALVE_Q>(arena, op.base + e[k].y, op.n, flags);
-          a = ru == rv;
-        }
-        if (i < op.count) op.out[i] = a;
-      }
-    }
+    if (r + 1 < nrounds && !grid_sync(bar, gen, flags, spin_limit)) break;
   }
 }
 

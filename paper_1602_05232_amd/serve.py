@@ -237,6 +237,22 @@ class GpuExecutor:
         self.images[s] = self.pool.save(gid)
         self.pool.remove(gid)
 
+    def checkpoint(self):
+        """State images of every stream seen so far (resident ones are saved
+        from the pool, evicted ones are already images).  Call when nothing
+        is in flight."""
+        self.torch.cuda.synchronize()
+        out = dict(self.images)
+        self.pool.set_stream(self.admin)
+        for s, gid in self.gid.items():
+            out[s] = self.pool.save(gid)
+        return out
+
+    def restore(self, images):
+        """Take over the images of a checkpoint: each stream is loaded from
+        its image when it is next admitted."""
+        self.images.update(images)
+
     def launch(self, ops):
         st = self.streams[self.next]
         self.next = (self.next + 1) % len(self.streams)

@@ -296,3 +296,20 @@ def test_bulk_find_compresses_every_endpoint(cc):
         assert (par[par[ends]] == par[ends]).all(), "a queried vertex does not point at its root"
     np.testing.assert_array_equal(g.labels().cpu().numpy(), ref.labels())
     g.close()
+
+
+@pytest.mark.parametrize("opts", [dict(update_mode=0), dict(update_mode=1), dict(update_mode=0, compress_linked=0)],
+                         ids=opt_id)
+def test_id_order_forest_invariants(cc, opts):
+    """Under id-order linking every parent pointer goes to a smaller id, so
+    each root is its tree's minimum; the number of roots equals n minus the
+    successful links; checked on the device state after every minibatch."""
+    s = synth.rmat_stream(scale=15, size_lo=9, size_hi=14, qbatch=16)
+    g = cc.Graph(s.n, **opts)
+    for i in range(s.num_batches):
+        g.bulk_update(dev(s.batch(i)))
+        par = np.frombuffer(bytes(g.save()), np.int32, offset=16)
+        assert (par <= np.arange(s.n)).all()
+        roots = int((par == np.arange(s.n)).sum())
+        assert roots == g.num_components() == g.count_roots()
+    g.close()

@@ -30,7 +30,8 @@ def small_graphs(G, seed=5):
 
 
 @pytest.mark.parametrize("opts", [dict(), dict(hook=1), dict(items=1, block=64, grid_cap=5),
-                                  dict(items=8, block=512, compress_linked=0, query_halving=0)],
+                                  dict(items=8, block=512, compress_linked=0, query_halving=0),
+                                  dict(one_launch=1), dict(one_launch=1, hook=1, items=1, grid_cap=3)],
                          ids=lambda o: ",".join("%s=%s" % kv for kv in sorted(o.items())) or "default")
 def test_pool_steps_match_oracle(cc, opts):
     G = 96
@@ -63,11 +64,12 @@ def test_pool_steps_match_oracle(cc, opts):
     pool.close()
 
 
-def test_pool_many_rounds_in_one_run(cc):
+@pytest.mark.parametrize("one_launch", [0, 1])
+def test_pool_many_rounds_in_one_run(cc, one_launch):
     # several operations per graph in one run: rounds must keep list order
     G = 24
     streams = small_graphs(G, seed=9)
-    pool = cc.Pool(sum(s.n for s in streams), G)
+    pool = cc.Pool(sum(s.n for s in streams), G, one_launch=one_launch)
     ids = [pool.add(s.n) for s in streams]
     ops, outs, want = [], [], []
     for g, s in enumerate(streams):

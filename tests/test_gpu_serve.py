@@ -54,3 +54,27 @@ def test_gpu_serving_matches_oracle(serve, budget_graphs):
         if r.kind == serve.QUERY:
             np.testing.assert_array_equal(r.out.cpu().numpy(), want[r.rid])
     ex.close()
+
+
+def test_gpu_serving_checkpoint_resume(serve):
+    """Serve the first half of a trace, checkpoint every stream, drop the
+    executor, resume the second half on a fresh one: the answers are those of
+    the uninterrupted run (the oracle's)."""
+    ns, reqs = make_trace(S=10, R=240, rate=5e4, seed=33, nmax=1 << 12)
+    want, _ = expected_answers(ns, reqs)
+    first, second = reqs[:120], reqs[120:]
+    ex = serve.GpuExecutor(max(ns) * 4, len(ns) + 1)
+    done = serve.Scheduler(ex, ns, max_inflight=2).run(to_gpu(serve, first))
+    images = ex.checkpoint()
+    ex.close()
+    t0 = min(r.arrival for r in second)
+    for r in second:
+        r.arrival -= t0
+    ex2 = serve.GpuExecutor(max(ns) * 4, len(ns) + 1)
+    ex2.restore(images)
+    done += serve.Scheduler(ex2, ns, max_inflight=2).run(to_gpu(serve, second))
+    torch.cuda.synchronize()
+    for r in done:
+        if r.kind == serve.QUERY:
+            np.testing.assert_array_equal(r.out.cpu().numpy(), want[r.rid], err_msg="request %d" % r.rid)
+    ex2.close()
