@@ -282,3 +282,30 @@ def test_pins_catch_planted_mistake(built_libs, tmp_path, name):
     except AssertionError:
         caught = True
     assert caught, "mutant %s survived the pins" % name
+
+
+def component_trace(s, points=10):
+    uf = oracle.UnionFind(s.n)
+    out = []
+    for i in range(s.num_batches):
+        uf.bulk_update(s.batch(i))
+        out.append((s.eoff[i + 1] / len(s.edges), uf.num_components()))
+    return out
+
+
+def test_stream_shapes_match_the_component_trends_of_section_6(built_libs):
+    """Section 6.2 describes the component counts along the paper's streams
+    (Fig. 2, whose curves are not in the text): local16 is connected around
+    the middle of the stream, rMat keeps many components to the end, and
+    random and local5 are almost indistinguishable until the end.  The
+    synthetic stand-ins reproduce those shapes (n = 2^16)."""
+    n = 1 << 16
+    loc16 = component_trace(synth.local_stream(n=n, degree=16, window=1 << 8, batch=1 << 14, qbatch=1))
+    first_one = next(f for f, c in loc16 if c == 1)
+    assert 0.3 <= first_one <= 0.7
+    rmat = component_trace(synth.rmat_stream(scale=16, size_lo=10, size_hi=14, qbatch=1))
+    assert rmat[-1][1] > 0.25 * n
+    rnd = component_trace(synth.er_stream(n=n, batches=20, batch=5 * n // 20, qbatch=1, probes=0))
+    loc5 = component_trace(synth.local_stream(n=n, degree=5, window=1 << 8, batch=5 * n // 20, qbatch=1))
+    for (f1, c1), (f2, c2) in zip(rnd[:-4], loc5[:-4]):
+        assert abs(f1 - f2) < 1e-9 and abs(c1 - c2) <= 0.05 * max(c1, c2) + 50
