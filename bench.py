@@ -18,6 +18,11 @@ Other workloads compare the forms of the path on their own configurations:
   serve64      request loop over 64 R-MAT scale-22 graphs, Poisson arrivals of
                70% updates / 30% queries: continuous batching vs serial plain,
                saturation throughput and p50/p99 latency
+  bigbatch     the R-MAT scale-24 and an Erdos-Renyi (n = 2^24, 5n edges) edge
+               set in 1, 8 and 64 equal minibatches: Bulk-Update throughput of
+               the fused (CAS) schedule under each linking order against the
+               contracting schedule (Algorithm 2 with rounds on A'')
+  components   number of components along each workload shape's stream
 
 Prints ONE JSON line.  `value` is (update edges + query pairs) per second of
 wall clock over the timed steps.
@@ -512,6 +517,75 @@ def run_serve(args):
     return res
 
 
+def run_bigbatch(args):
+    """Update-only throughput against minibatch size, fused vs contracting."""
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_1602_05232_amd as ccgpu
+    from paper_1602_05232_amd import tuning
+
+    graphs = {
+        "rmat24": lambda: synth.rmat_stream(scale=24, qbatch=1, probes=0),
+        "er24": lambda: synth.er_stream(n=1 << 24, batches=1, batch=5 << 24, qbatch=1, probes=0),
+    }
+    schedules = {
+        "fused-rank": tuning.plain_options(1 << 24, "rmat"),
+        "fused-id": dict(update_mode=0, hook=0, block=1024, compress_linked=0),
+        "fused-hash": dict(update_mode=0, hook=1, block=1024, compress_linked=0),
+        "contract-id": dict(update_mode=2, hook=0),
+        "contract-hash": dict(update_mode=2, hook=1),
+    }
+    table, best_rate, best_cfg = {}, 0.0, None
+    total_t, total_e = 0.0, 0
+    for gname, make in graphs.items():
+        s = make()
+        M = len(s.edges)
+        E = torch.from_numpy(s.edges).cuda()
+        for k in (1, 8, 64):
+            bounds = [M * i // k for i in range(k + 1)]
+            comps = None
+            for sname, opts in schedules.items():
+                g = ccgpu.Graph(s.n, **opts)
+                g.reserve(max(bounds[i + 1] - bounds[i] for i in range(k)))
+                times = []
+                for it in range(args.warmup + max(1, args.steps)):
+                    g.reset()
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    for i in range(k):
+                        g.bulk_update(E[bounds[i]:bounds[i + 1]])
+                    c = g.num_components()
+                    dt = time.perf_counter() - t0
+                    if it >= args.warmup:
+                        times.append(dt)
+                if g.sync() != 0:
+                    raise SystemExit("device reported an error (%s, %s, k=%d)" % (gname, sname, k))
+                g.close()
+                assert comps is None or c == comps, "component counts differ between schedules"
+                comps = c
+                t = min(times)
+                total_t += sum(times)
+                total_e += M * len(times)
+                rate = M / t
+                table.setdefault(gname, {}).setdefault("minibatches=%d" % k, {})[sname] = {
+                    "edges_per_s": rate, "ms": t * 1e3}
+                log("%s k=%d %s: %.3f ms, %.3g edges/s, components=%d" % (gname, k, sname, t * 1e3, rate, c))
+                if gname == "rmat24" and k == 1 and rate > best_rate:
+                    best_rate, best_cfg = rate, sname
+        del E
+        torch.cuda.empty_cache()
+    res = result(total_e / total_t, max(1, args.steps), args.warmup, total_t, {
+        "workload": "bigbatch", "graphs": {"rmat24": "R-MAT scale 24, 2^28 edges",
+                                           "er24": "n = 2^24, 5n uniform edges"},
+        "minibatches": [1, 8, 64], "schedules": schedules})
+    res["unit"] = "edges/s (update only)"
+    res["table"] = table
+    res["best_rmat24_one_minibatch"] = best_cfg
+    return res
+
+
 def run_components(args):
     """Number of components against the fraction of the stream consumed, for
     each workload shape at n = 2^24 (the measurement behind Fig. 2)."""
@@ -565,7 +639,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat24",
-                    choices=["rmat24", "grid4096", "batched1024", "serve64", "components"])
+                    choices=["rmat24", "grid4096", "batched1024", "serve64", "bigbatch", "components"])
     ap.add_argument("--requests", type=int, default=1024, help="requests of the serving trace")
     ap.add_argument("--serve-scale", type=int, default=22, help="R-MAT scale of each served graph")
     ap.add_argument("--scale", type=int, default=24, help="R-MAT scale of the rmat24 workload")
@@ -587,7 +661,7 @@ def main():
         import __graft_entry__
         __graft_entry__.build()
     res = {"rmat24": run_rmat, "grid4096": run_grid, "batched1024": run_batched,
-           "serve64": run_serve, "components": run_components}[args.workload](args)
+           "serve64": run_serve, "bigbatch": run_bigbatch, "components": run_components}[args.workload](args)
     print(json.dumps(res), flush=True)
 
 

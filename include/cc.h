@@ -61,7 +61,14 @@ enum cc_option {
    * relabels edges by their roots and compacts the pairs with distinct roots
    * (Algorithm 2, lines 1-2) into a live list, a link kernel joins the live
    * root pairs, a compress kernel points the linked roots at their new root.
-   * Default 0. */
+   * 2 = contracting: Algorithm 2 with its connected-components step done on
+   * the contracted edge list A'' by rounds of hooking and shortcutting (one
+   * cooperative launch; 8 bytes of scratch per edge of the largest
+   * minibatch; each round's work is linear in the surviving root pairs, not
+   * in the minibatch; the open question of Section 7 about very large
+   * minibatches).  Id and hashed orders only, not available during capture,
+   * at most 2^31 - 1 edges per call.
+   * Union by rank (CC_OPT_HOOK 2) takes schedule 0 only.  Default 0. */
   CC_OPT_UPDATE_MODE = 1,
   CC_OPT_BLOCK = 2,          /* threads per block, multiple of 64 in [64, 1024]; default 256 */
   CC_OPT_ITEMS = 3,          /* edges (or pairs) per thread: 1, 2, 4 or 8, or 0 = chosen per
@@ -70,7 +77,10 @@ enum cc_option {
   CC_OPT_COMPRESS_EVERY = 5, /* k > 0: after every k-th update point every vertex at its
                                 root (full pass over n); 0 = never (default) */
   CC_OPT_HOOK = 6,           /* linking order: 0 = by vertex id, the smaller id becomes
-                                the root (default); 1 = by a hashed priority (fmix32) */
+                                the root (default); 1 = by a hashed priority (fmix32);
+                                2 = union by rank (the balanced linking of Section 4
+                                with ranks in place of sizes; a root's rank sits in
+                                bits 27-31 of its word, so n <= 2^27) */
   CC_OPT_GRID_CAP = 7,       /* upper bound on blocks per launch (grid-stride beyond it);
                                 default 4096 */
   /* Fused schedule: 1 = record the roots each update links and afterwards
@@ -116,8 +126,10 @@ int cc_set_stream(cc_graph* g, void* stream);
 int cc_set_option(cc_graph* g, int key, int64_t value);
 int cc_get_option(cc_graph* g, int key, int64_t* value);
 
-/* Pre-size the scratch used by the split update schedule for minibatches of
- * up to max_batch edges, so that no later call allocates.  Waits for the
+/* Pre-size the scratch used by the split update schedule (or by the
+ * contracting schedule, when that is the schedule set at the time of the
+ * call) for minibatches of up to max_batch edges, so that no later call
+ * allocates.  Waits for the
  * stream if an existing buffer is replaced. */
 int cc_reserve(cc_graph* g, int64_t max_batch);
 

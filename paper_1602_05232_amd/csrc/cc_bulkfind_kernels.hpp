@@ -37,7 +37,8 @@ struct BulkFindScratch {
   int32_t* f0;        // frontier ping
   int32_t* f1;        // frontier pong
   unsigned* ctl;      // [0..2] frontier counts (ring), [3] trail count,
-                      // [5..7] Phase II change flags (ring), [8..10] barrier
+                      // [5..7] Phase II change flags (ring),
+                      // [16, 16 + kBarWords) device-wide barrier
 };
 
 // First visit of v?  A plain read skips the atomic for vertices already seen
@@ -47,6 +48,8 @@ __device__ __forceinline__ bool test_and_set(uint32_t* bits, int32_t v) {
   if (ld((const int32_t*)bits + (v >> 5)) & (int32_t)m) return false;
   return (atomicOr(bits + (v >> 5), m) & m) == 0u;
 }
+
+constexpr int kBulkFindCtlWords = 16 + kBarWords;
 
 // Append one item with one atomic per wavefront.
 __device__ __forceinline__ unsigned wave_append(unsigned* counter, bool want) {
@@ -76,7 +79,7 @@ __global__ void k_bulk_find(int32_t* __restrict__ parent, const int2* __restrict
   constexpr bool R = is_ranked<Ord>::value;
   const int64_t gsize = (int64_t)gridDim.x * blockDim.x;
   const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  unsigned* bar = sc.ctl + 8;
+  unsigned* bar = sc.ctl + 16;
   unsigned gen = 0;
   bool alive = true;
 

@@ -59,7 +59,7 @@ struct Tuning {
 inline bool set_tuning(Tuning* t, int key, int64_t v) {
   switch (key) {
     case CC_OPT_UPDATE_MODE:
-      if (v != 0 && v != 1) return false;
+      if (v < 0 || v > 2) return false;
       t->mode = (int)v;
       return true;
     case CC_OPT_BLOCK:
@@ -122,6 +122,15 @@ inline bool get_tuning(const Tuning* t, int key, int64_t* v) {
     case CC_OPT_ONE_LAUNCH: *v = t->one_launch; return true;
     default: return false;
   }
+}
+
+// Upper bound on the blocks of a cooperative launch (every block resident
+// at once).  One block per compute unit is left free: a kernel whose
+// registers fill the register file at the occupancy calculator's maximum did
+// not get every block of such a grid resident at the same time (the device
+// barrier then waited out its spin limit), while one block less per CU did.
+inline int64_t coop_limit(int per_cu, int cus) {
+  return (int64_t)(per_cu > 1 ? per_cu - 1 : 1) * cus;
 }
 
 // Items per thread for a launch over m items: the requested value, or with

@@ -14,6 +14,7 @@
 #include "cc_kernels.hpp"
 #include "cc_vertex_kernels.hpp"
 #include "cc_bulkfind_kernels.hpp"
+#include "cc_contract_kernels.hpp"
 #include "cc_stream_kernels.hpp"
 
 using namespace ccdev;
@@ -55,7 +56,9 @@ struct cc_graph {
   int* flags = nullptr;
   int2* live = nullptr;
   unsigned* live_ctl = nullptr;  // [0] live count, [1] finished blocks, [2..3] same for hooked
+  unsigned* gbar = nullptr;      // device-wide barrier of cc_bulk_stream (kBarWords)
   int32_t* hooked = nullptr;     // roots linked by the last fused update (n entries)
+  unsigned* contract_ctl = nullptr;  // survivor counters + barrier of the contracting update
   BulkFindScratch bf{};          // Bulk-Find scratch (allocated on first use)
   bool bf_ready = false;
   int64_t live_cap = 0;
@@ -124,7 +127,7 @@ int alloc_bulkfind(cc_graph* g) {
   const size_t n = (size_t)g->n, words = (n + 31) / 32;
   bool ok = hipMalloc(&b.visited, words * 4) == hipSuccess && hipMalloc(&b.trail, n * 4) == hipSuccess &&
             hipMalloc(&b.f0, n * 4) == hipSuccess && hipMalloc(&b.f1, n * 4) == hipSuccess &&
-            hipMalloc(&b.ctl, 64) == hipSuccess;
+            hipMalloc(&b.ctl, kBulkFindCtlWords * sizeof(unsigned)) == hipSuccess;
   if (!ok) {
     free_bulkfind(g);
     cc_set_error("Bulk-Find scratch allocation (about 12 bytes per vertex) failed");
@@ -237,8 +240,8 @@ int launch_bulk_find_t(cc_graph* g, const int2* items, int64_t count, uint8_t* o
   HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bulk_find<KIND, Ord>, block, 0));
   HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device));
   int64_t grid = (2 * count + block - 1) / block;
-  grid = std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(grid, (int64_t)per_cu * cus), 1024));
-  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, g->stream, g->bf.ctl, 16);
+  grid = std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(grid, cc::coop_limit(per_cu, cus)), 1024));
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, g->stream, g->bf.ctl, kBulkFindCtlWords);
   HIP_TRY(hipGetLastError());
   int32_t* parent = g->parent;
   int32_t n = (int32_t)g->n;
@@ -249,6 +252,53 @@ int launch_bulk_find_t(cc_graph* g, const int2* items, int64_t count, uint8_t* o
   void* args[] = {&parent, &items, &count, &n, &out, &sc, &slots, &flags, &spin};
   HIP_TRY(hipLaunchCooperativeKernel((const void*)k_bulk_find<KIND, Ord>, dim3((unsigned)grid), dim3(block), args,
                                      0, g->stream));
+  return CC_OK;
+}
+
+int alloc_contract_ctl(cc_graph* g) {
+  if (g->contract_ctl) return CC_OK;
+  if (hipMalloc(&g->contract_ctl, (size_t)kContractCtlWords * sizeof(unsigned)) != hipSuccess) {
+    g->contract_ctl = nullptr;
+    cc_set_error("hipMalloc of the contracting update's counters failed");
+    return CC_ENOMEM;
+  }
+  return CC_OK;
+}
+
+// Blocks of the contracting update's cooperative launch for m edges.
+template <class Ord>
+int contract_grid(cc_graph* g, int64_t m, int64_t* grid) {
+  const int block = 256;
+  int per_cu = 0, cus = 0;
+  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_contract<Ord>, block, 0));
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device));
+  int64_t b = (m + 4 * block - 1) / (4 * block);
+  b = std::min<int64_t>(b, cc::coop_limit(per_cu, cus));
+  b = std::min<int64_t>(b, (int64_t)g->tune.grid_cap);
+  *grid = std::max<int64_t>(b, 1);
+  return CC_OK;
+}
+
+template <class Ord>
+int launch_contract_t(cc_graph* g, const int2* e, int64_t m) {
+  int64_t grid = 0;
+  int rc = contract_grid<Ord>(g, m, &grid);
+  if (rc == CC_OK) rc = alloc_contract_ctl(g);
+  int64_t seg_cap = (m + grid - 1) / grid;
+  if (rc == CC_OK) rc = alloc_live(g, seg_cap * grid);
+  if (rc != CC_OK) return rc;
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, g->stream, g->contract_ctl, kContractCtlWords);
+  HIP_TRY(hipGetLastError());
+  int32_t* parent = g->parent;
+  int32_t n = (int32_t)g->n;
+  int2* list = g->live;
+  unsigned* ctl = g->contract_ctl;
+  unsigned long long* slots = g->slots;
+  int* flags = g->flags;
+  unsigned spin = (unsigned)g->tune.spin_limit;
+  void* args[] = {&parent, &e, &m, &n, &list, &seg_cap, &ctl, &slots, &flags, &spin};
+  HIP_TRY(hipLaunchCooperativeKernel((const void*)k_contract<Ord>, dim3((unsigned)grid), dim3(256), args, 0,
+                                     g->stream));
   return CC_OK;
 }
 
@@ -287,6 +337,7 @@ extern "C" cc_graph* cc_create(int64_t n) {
     (void)hipFree(g->red);
     (void)hipFree(g->flags);
     (void)hipFree(g->live_ctl);
+    (void)hipFree(g->gbar);
     delete g;
     return nullptr;
   };
@@ -297,6 +348,7 @@ extern "C" cc_graph* cc_create(int64_t n) {
   if ((e = hipMalloc(&g->red, 64)) != hipSuccess) return fail("red", e);
   if ((e = hipMalloc(&g->flags, 64)) != hipSuccess) return fail("flags", e);
   if ((e = hipMalloc(&g->live_ctl, 64)) != hipSuccess) return fail("live_ctl", e);
+  if ((e = hipMalloc(&g->gbar, kBarWords * sizeof(unsigned))) != hipSuccess) return fail("gbar", e);
   if ((e = hipMemsetAsync(g->flags, 0, 64, g->stream)) != hipSuccess) return fail("memset", e);
   if ((e = hipMemsetAsync(g->live_ctl, 0, 64, g->stream)) != hipSuccess) return fail("memset", e);
   if (launch_init(g) != CC_OK) return fail("init launch", hipGetLastError());
@@ -318,6 +370,10 @@ extern "C" int cc_destroy(cc_graph* g) {
   (void)hipFree(g->flags);
   (void)hipFree(g->live);
   (void)hipFree(g->live_ctl);
+  (void)hipFree(g->gbar);
+  (void)hipFree(g->hooked);
+  (void)hipFree(g->contract_ctl);
+  if (g->bf_ready) free_bulkfind(g);
   delete g;
   return CC_OK;
 }
@@ -360,6 +416,13 @@ extern "C" int cc_reserve(cc_graph* g, int64_t max_batch) {
   DeviceGuard dg(g->device);
   int rc = alloc_hooked(g);
   if (rc != CC_OK) return rc;
+  if (g->tune.mode == 2 && max_batch > 0) {
+    int64_t grid = 0;
+    rc = g->tune.hook == 1 ? contract_grid<ByHash>(g, max_batch, &grid) : contract_grid<ById>(g, max_batch, &grid);
+    if (rc == CC_OK) rc = alloc_contract_ctl(g);
+    if (rc != CC_OK) return rc;
+    return alloc_live(g, (max_batch + grid - 1) / grid * grid);
+  }
   return alloc_live(g, max_batch);
 }
 
@@ -384,11 +447,22 @@ extern "C" int cc_bulk_update(cc_graph* g, const int32_t* edges, int64_t m) {
     return rc;
   }
   const bool hashed = g->tune.hook == 1, ranked = g->tune.hook == 2;
-  if (ranked && g->tune.mode == 1) {
+  if (ranked && g->tune.mode != 0) {
     cc_set_error("cc_bulk_update: union by rank runs with the fused schedule only");
     return CC_EINVAL;
   }
-  if (g->tune.mode == 1) {
+  if (g->tune.mode == 2) {
+    if (g->capturing) {
+      cc_set_error("cc_bulk_update: the contracting update is not available while capturing");
+      return CC_EINVAL;
+    }
+    if (m > 0x7fffffffLL) {
+      cc_set_error("cc_bulk_update: the contracting update takes at most 2^31-1 edges per call");
+      return CC_EINVAL;
+    }
+    int rc = hashed ? launch_contract_t<ByHash>(g, e, m) : launch_contract_t<ById>(g, e, m);
+    if (rc != CC_OK) return rc;
+  } else if (g->tune.mode == 1) {
     if (g->capturing && m > g->live_cap) {
       cc_set_error("cc_bulk_update: split update of %lld edges exceeds the reserved %lld during capture",
                    (long long)m, (long long)g->live_cap);
@@ -645,10 +719,10 @@ int launch_stream(cc_graph* g, int64_t batches, const int32_t* edges, const int6
   HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_stream<Ord>, block, 0));
   HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device));
   int64_t grid = (max_items + block - 1) / block;
-  grid = std::min<int64_t>(grid, (int64_t)per_cu * cus);
+  grid = std::min<int64_t>(grid, cc::coop_limit(per_cu, cus));
   grid = std::min<int64_t>(grid, 1024);
   grid = std::max<int64_t>(grid, 1);
-  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, g->stream, g->live_ctl + 4, 3);
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, g->stream, g->gbar, kBarWords);
   HIP_TRY(hipGetLastError());
   int32_t* parent = g->parent;
   const int2* e = reinterpret_cast<const int2*>(edges);
@@ -656,7 +730,7 @@ int launch_stream(cc_graph* g, int64_t batches, const int32_t* edges, const int6
   int32_t n = (int32_t)g->n;
   unsigned long long* slots = g->slots;
   int* flags = g->flags;
-  unsigned* bar = g->live_ctl + 4;
+  unsigned* bar = g->gbar;
   unsigned spin = (unsigned)g->tune.spin_limit;
   void* args[] = {&parent, &batches, &e, &eoff, &p, &qoff, &out, &n, &slots, &flags, &bar, &spin};
   HIP_TRY(hipLaunchCooperativeKernel((const void*)k_stream<Ord>, dim3((unsigned)grid), dim3(block), args, 0,

@@ -153,9 +153,9 @@ int launch_rounds_t(cc_pool* p, const RingSlot* s, int rounds, uint32_t max_tile
   int per_cu = 0, cus = 0;
   HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pool_rounds<ITEMS, HASH, HALVE>, B, 0));
   HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device));
-  int64_t grid = std::min<int64_t>(std::min<int64_t>(max_tiles, (int64_t)per_cu * cus), p->tune.grid_cap);
+  int64_t grid = std::min<int64_t>(std::min<int64_t>(max_tiles, cc::coop_limit(per_cu, cus)), p->tune.grid_cap);
   grid = std::max<int64_t>(grid, 1);
-  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, p->stream, p->bar, 3);
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, p->stream, p->bar, kBarWords);
   HIP_TRY(hipGetLastError());
   const OpDesc* ops = s->dev;
   const int32_t* rstart = s->meta_dev;
@@ -248,7 +248,7 @@ extern "C" cc_pool* cc_pool_create(int64_t capacity, int32_t max_graphs) {
   if (hipMalloc(&p->arena, (size_t)capacity * 4) != hipSuccess) return fail("arena");
   if (hipMalloc(&p->glinks, (size_t)max_graphs * kPoolLinkStride * 8) != hipSuccess) return fail("links");
   if (hipMalloc(&p->flags, 64) != hipSuccess) return fail("flags");
-  if (hipMalloc(&p->bar, 64) != hipSuccess) return fail("bar");
+  if (hipMalloc(&p->bar, kBarWords * sizeof(unsigned)) != hipSuccess) return fail("bar");
   if (hipMemsetAsync(p->flags, 0, 64, p->stream) != hipSuccess) return fail("memset");
   if (hipMemsetAsync(p->glinks, 0, (size_t)max_graphs * kPoolLinkStride * 8, p->stream) != hipSuccess)
     return fail("memset");

@@ -5,13 +5,21 @@
 // boundary per operation.  Meant for streams of many small minibatches,
 // whose cost in separate launches is mostly launch and drain latency.
 //
-// The grid is launched cooperatively (all blocks resident).  A barrier:
-// every wavefront makes its writes visible device-wide (agent-scope release
-// fence), one thread per block counts the block in, the last arrival
-// publishes the next generation, the others wait for it, and then every
-// wavefront drops stale cached lines (agent-scope acquire fence).  Waiting is
-// bounded: past the spin limit a block raises the timeout flag and an abort
-// word, and every block leaves the kernel at its next barrier.
+// The grid is launched cooperatively (all blocks resident).  A barrier: the
+// block's threads meet at a workgroup barrier, then one thread per block
+// makes the block's writes visible device-wide (agent-scope release fence:
+// every wavefront of the block has passed the workgroup barrier, so one
+// fence covers them, as in the usual grid-sync construction), counts the
+// block in, and either publishes the next generation (last arrival) or
+// waits for it; it then drops stale cached lines (agent-scope acquire
+// fence) before the block's threads continue.  One fence pair per block
+// instead of one per wavefront: each fence writes back or invalidates the
+// whole L2 of the XCD, and thousands of them per barrier dominated its cost.
+// The arrival counter, the generation and the abort word sit on separate
+// 128-byte lines, so waiting blocks polling the generation do not contend
+// with arrivals.  Waiting is bounded: past the spin limit a block raises the
+// timeout flag and the abort word, and every block leaves the kernel at its
+// next barrier.
 #pragma once
 
 #include "cc_kernels.hpp"
@@ -19,40 +27,48 @@
 namespace ccdev {
 namespace {
 
-// bar[0] arrivals (monotone within a launch), bar[1] generation, bar[2] abort;
-// all three are zero at launch.
+// Barrier state: bar[0] arrivals (monotone within a launch), bar[32]
+// generation, bar[64] abort; all zero at launch.
+constexpr int kBarWords = 96;
+
+__device__ __forceinline__ unsigned bar_load(unsigned* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ bool grid_sync(unsigned* bar, unsigned& gen, int* flags, unsigned spin_limit) {
   __shared__ int ok;
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
   if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     const unsigned target = gen + 1;
     int good = 1;
     const unsigned arrived = __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
     if (arrived == gridDim.x * target) {
-      __hip_atomic_store(bar + 1, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(bar + 32, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
       unsigned spins = 0;
-      while (__hip_atomic_load(bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-        if (__hip_atomic_load(bar + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
-          good = 0;
-          break;
-        }
+      while (bar_load(bar + 32) < target) {
         __builtin_amdgcn_s_sleep(2);
-        if (++spins > spin_limit) {
-          __hip_atomic_store(bar + 2, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          raise_flag(flags, kFlagTimeout);
-          good = 0;
-          break;
+        if ((++spins & 31u) == 0u) {
+          if (bar_load(bar + 64) != 0u) {
+            good = 0;
+            break;
+          }
+          if (spins > spin_limit) {
+            __hip_atomic_store(bar + 64, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            raise_flag(flags, kFlagTimeout);
+            good = 0;
+            break;
+          }
         }
       }
     }
-    if (__hip_atomic_load(bar + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) good = 0;
+    if (bar_load(bar + 64) != 0u) good = 0;
     ok = good;
     gen = target;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   return ok != 0;
 }
 

@@ -77,11 +77,16 @@ def test_capture_rejects_waiting_calls(cc):
     g = cc.Graph(100, stream=st)
     L = cc.lib()
     import ctypes
+    e = torch.zeros((4, 2), dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
     assert L.cc_capture_begin(g.handle) == 0
     v = ctypes.c_int64()
     assert L.cc_num_components(g.handle, ctypes.byref(v)) == cc.cc.CC_EINVAL
     assert L.cc_sync(g.handle) == cc.cc.CC_EINVAL
     assert L.cc_capture_begin(g.handle) == cc.cc.CC_EINVAL
+    assert L.cc_set_option(g.handle, 1, 2) == 0  # the contracting update is one cooperative launch
+    assert L.cc_bulk_update(g.handle, ctypes.c_void_p(e.data_ptr()), 4) == cc.cc.CC_EINVAL
+    assert L.cc_set_option(g.handle, 1, 0) == 0
     x = ctypes.c_void_p()
     assert L.cc_capture_end(g.handle, ctypes.byref(x)) == 0
     assert L.cc_exec_destroy(x.value) == 0

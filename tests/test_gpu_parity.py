@@ -24,6 +24,9 @@ OPTION_SETS = [
     dict(update_mode=0, hook=1, items=8, block=512, grid_cap=5),
     dict(update_mode=0, hook=2),
     dict(update_mode=0, hook=2, compress_linked=0, items=8, query_halving=0, compress_every=2),
+    dict(update_mode=2),
+    dict(update_mode=2, hook=1, grid_cap=3),
+    dict(update_mode=2, query_halving=0, compress_every=2),
     dict(find=1),
     dict(find=1, hook=2),
 ]
@@ -94,7 +97,8 @@ def test_rmat_small(cc, opts):
     run_parity(cc, synth.rmat_stream(scale=16, size_lo=8, size_hi=16, qbatch=1 << 12), opts)
 
 
-@pytest.mark.parametrize("opts", OPTION_SETS[:4] + OPTION_SETS[-2:], ids=opt_id)
+@pytest.mark.parametrize("opts", OPTION_SETS[:4] + [dict(update_mode=2), dict(update_mode=2, hook=1)]
+                         + OPTION_SETS[-2:], ids=opt_id)
 def test_grid_small(cc, opts):
     s = synth.grid_stream_cfg(W=256, H=256, batch=1 << 12, qbatch=1 << 10)
     ref = run_parity(cc, s, opts, label_every=4)
@@ -102,7 +106,7 @@ def test_grid_small(cc, opts):
 
 
 @pytest.mark.parametrize("which", ["grid3d", "local"])
-@pytest.mark.parametrize("opts", [dict(), dict(hook=2), dict(update_mode=1)], ids=opt_id)
+@pytest.mark.parametrize("opts", [dict(), dict(hook=2), dict(update_mode=1), dict(update_mode=2)], ids=opt_id)
 def test_more_workload_shapes(cc, which, opts):
     if which == "grid3d":
         s = synth.grid3d_stream_cfg(L=40, batch=1 << 13, qbatch=1 << 10)
@@ -111,7 +115,7 @@ def test_more_workload_shapes(cc, which, opts):
     run_parity(cc, s, opts, label_every=3)
 
 
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 def test_ragged_sizes(cc, mode):
     sizes = [1, 63, 64, 65, 255, 257, 1023, 1025, 4095, 4097, 0, 3, 12289]
     n = 5000
@@ -122,7 +126,7 @@ def test_ragged_sizes(cc, mode):
     run_parity(cc, s, dict(update_mode=mode, items=4, block=256))
 
 
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 def test_edge_cases(cc, mode):
     n = 1 << 12
     g = cc.Graph(n, update_mode=mode)
@@ -151,7 +155,8 @@ def test_edge_cases(cc, mode):
 
 
 @pytest.mark.parametrize("opts", [dict(update_mode=0), dict(update_mode=1), dict(update_mode=0, hook=1),
-                                  dict(update_mode=0, hook=2)], ids=opt_id)
+                                  dict(update_mode=0, hook=2), dict(update_mode=2), dict(update_mode=2, hook=1)],
+                         ids=opt_id)
 def test_deep_chain(cc, opts):
     # reversed path in one minibatch, then in single-edge minibatches
     n = 1 << 20
@@ -174,7 +179,7 @@ def test_deep_chain(cc, opts):
     g.close()
 
 
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 def test_invalid_ids(cc, mode):
     n = 10
     g = cc.Graph(n, update_mode=mode)
@@ -196,11 +201,14 @@ def test_argument_errors(cc):
     g = cc.Graph(16)
     L = cc.lib()
     assert L.cc_set_option(g.handle, 6, 3) == cc.cc.CC_EINVAL
-    g2 = cc.Graph(16, hook=2, update_mode=1)  # rank linking needs the fused schedule
-    assert L.cc_bulk_update(g2.handle, g2.handle, 0) == cc.cc.CC_OK
-    with pytest.raises(cc.CCError):
-        g2.bulk_update(dev([[1, 2]]))
-    g2.close()
+    for mode in (1, 2):
+        g2 = cc.Graph(16, hook=2, update_mode=mode)  # rank linking needs the fused schedule
+        assert L.cc_bulk_update(g2.handle, g2.handle, 0) == cc.cc.CC_OK
+        with pytest.raises(cc.CCError):
+            g2.bulk_update(dev([[1, 2]]))
+        assert g2.num_components() == 16
+        g2.close()
+    assert L.cc_set_option(g.handle, 1, 3) == cc.cc.CC_EINVAL
     assert L.cc_bulk_update(g.handle, None, 3) == cc.cc.CC_EINVAL
     assert L.cc_bulk_update(g.handle, None, -1) == cc.cc.CC_EINVAL
     assert L.cc_bulk_query(g.handle, None, 2, None) == cc.cc.CC_EINVAL
@@ -247,7 +255,7 @@ def test_order_independence_and_reset(cc):
     g = cc.Graph(s.n)
     g.bulk_update(dev(s.edges))
     want = g.labels().cpu().numpy()
-    for mode in (0, 1):
+    for mode in (0, 1, 2):
         g.set_option("update_mode", mode)
         g.reset()
         assert g.num_components() == s.n
@@ -298,8 +306,8 @@ def test_bulk_find_compresses_every_endpoint(cc):
     g.close()
 
 
-@pytest.mark.parametrize("opts", [dict(update_mode=0), dict(update_mode=1), dict(update_mode=0, compress_linked=0)],
-                         ids=opt_id)
+@pytest.mark.parametrize("opts", [dict(update_mode=0), dict(update_mode=1), dict(update_mode=0, compress_linked=0),
+                                  dict(update_mode=2)], ids=opt_id)
 def test_id_order_forest_invariants(cc, opts):
     """Under id-order linking every parent pointer goes to a smaller id, so
     each root is its tree's minimum; the number of roots equals n minus the
