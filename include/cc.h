@@ -97,8 +97,9 @@ enum cc_option {
    * (with path halving; default).  1 = Bulk-Find (Section 5, Algorithm 4):
    * all endpoints of a Bulk-Update or Bulk-Query are resolved together, flows
    * that meet are merged, and every traversed vertex is pointed at its root;
-   * one cooperative launch per bulk operation, about 12 bytes of scratch per
-   * vertex, not available during capture. */
+   * one cooperative launch per bulk operation; scratch of about 8 bytes per
+   * vertex plus 8 bytes per item of the largest bulk operation; not
+   * available during capture. */
   CC_OPT_FIND = 10,
   /* Pools only (cc_pool_run): 1 = all rounds of a run in one cooperative
    * launch, separated by device-wide barriers, instead of one launch per

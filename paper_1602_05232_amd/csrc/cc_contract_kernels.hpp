@@ -34,7 +34,8 @@
 // cannot do; the form takes the id and hashed-priority orders only.
 #pragma once
 
-#include "cc_bulkfind_kernels.hpp"
+#include "cc_grid.hpp"
+#include "cc_kernels.hpp"
 
 namespace ccdev {
 namespace {
@@ -61,64 +62,14 @@ __device__ __forceinline__ int hook(int32_t* parent, int32_t loser, int32_t winn
   return atomicExch(parent + loser, winner) == loser;
 }
 
-// Exclusive scan of per-thread counts over the block; returns this thread's
-// offset and the block total.  Every thread of the block calls it.
-__device__ __forceinline__ int block_scan(int cnt, int* total, int* wave_off) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  int incl = cnt;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const int y = __shfl_up(incl, off, 64);
-    if (lane >= off) incl += y;
-  }
-  if (lane == 63) wave_off[wid] = incl;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int acc = 0;
-    for (int w = 0; w < nw; ++w) {
-      const int c = wave_off[w];
-      wave_off[w] = acc;
-      acc += c;
-    }
-    wave_off[16] = acc;
-  }
-  __syncthreads();
-  const int off = wave_off[wid] + incl - cnt;
-  *total = wave_off[16];
-  __syncthreads();  // wave_off is reused by the next call
-  return off;
-}
-
-// Survivor totals: one group of kCountSlots counters per round (a ring of
-// three groups), each block adding to the counter of its index mod
-// kCountSlots.  A single counter would take one same-address device atomic
-// per block per round, and such atomics are served one at a time.
-constexpr int kCountSlots = 32;
-constexpr int kCountStride = 32;  // 128 B apart
-constexpr int kContractCtlWords = 3 * kCountSlots * kCountStride + kBarWords;
-constexpr int kMaxRounds = 64;
-
-__device__ __forceinline__ unsigned* count_group(unsigned* ctl, int round) {
-  return ctl + (round % 3) * kCountSlots * kCountStride;
-}
-
-__device__ __forceinline__ unsigned group_total(unsigned* grp, int* red) {
-  if (threadIdx.x < 64) {
-    int v = threadIdx.x < kCountSlots ? (int)ld_count(grp + threadIdx.x * kCountStride) : 0;
-    v = wave_sum(v);
-    if (threadIdx.x == 0) *red = v;
-  }
-  __syncthreads();
-  const unsigned t = (unsigned)*red;
-  __syncthreads();
-  return t;
-}
-
 // The list is split into one segment per block: block b owns edges
 // [b * seg_cap, (b + 1) * seg_cap) of the minibatch and the same index range
 // of `list`, keeps its survivors there (compacted in place round after
 // round) and is the only block that touches them, so no list position is
 // ever reserved with a global atomic.
+constexpr int kContractCtlWords = kCountWords + kBarWords;
+constexpr int kMaxRounds = 64;
+
 // ctl: kContractCtlWords words, zero at launch (count groups, then barrier).
 template <class Ord>
 __global__ void k_contract(int32_t* __restrict__ parent, const int2* __restrict__ edges, int64_t m, int32_t n,
@@ -131,7 +82,7 @@ __global__ void k_contract(int32_t* __restrict__ parent, const int2* __restrict_
   const int64_t e0 = (int64_t)blockIdx.x * seg_cap;
   const int64_t e1 = e0 + seg_cap < m ? e0 + seg_cap : m;
   int2* seg = list + e0;
-  unsigned* bar = ctl + 3 * kCountSlots * kCountStride;
+  unsigned* bar = ctl + kCountWords;
   unsigned gen = 0;
   const Ord ord{};
   const int slot = (int)(blockIdx.x % kCountSlots) * kCountStride;
@@ -173,9 +124,7 @@ __global__ void k_contract(int32_t* __restrict__ parent, const int2* __restrict_
   int links = 0;
   for (int round = 0; alive; ++round) {
     if (group_total(count_group(ctl, round), &red) == 0u) break;
-    // the group added to in round r + 1; everyone last read it at the start
-    // of round r - 1, two barriers ago
-    if (blockIdx.x == 0 && tid < kCountSlots) st_count(count_group(ctl, round + 2) + tid * kCountStride, 0u);
+    clear_group_ahead(ctl, round);
 
     // hook
     for (int64_t i = tid; i < cnt; i += B) {

@@ -61,6 +61,7 @@ struct cc_graph {
   unsigned* contract_ctl = nullptr;  // survivor counters + barrier of the contracting update
   BulkFindScratch bf{};          // Bulk-Find scratch (allocated on first use)
   bool bf_ready = false;
+  int64_t bf_seg0_entries = 0;   // allocated level-0 entries
   int64_t live_cap = 0;
   int64_t updates = 0;
   bool capturing = false;
@@ -105,12 +106,12 @@ int alloc_hooked(cc_graph* g) {
 void free_bulkfind(cc_graph* g) {
   BulkFindScratch& b = g->bf;
   (void)hipFree(b.visited);
-  (void)hipFree(b.trail);
-  (void)hipFree(b.f0);
-  (void)hipFree(b.f1);
+  (void)hipFree(b.seg0);
+  (void)hipFree(b.log);
   (void)hipFree(b.ctl);
   b = BulkFindScratch{};
   g->bf_ready = false;
+  g->bf_seg0_entries = 0;
 }
 
 // Bulk-Find keeps its visited bitmap all clear between calls; this
@@ -125,12 +126,13 @@ int alloc_bulkfind(cc_graph* g) {
   if (g->bf_ready) return CC_OK;
   BulkFindScratch& b = g->bf;
   const size_t n = (size_t)g->n, words = (n + 31) / 32;
-  bool ok = hipMalloc(&b.visited, words * 4) == hipSuccess && hipMalloc(&b.trail, n * 4) == hipSuccess &&
-            hipMalloc(&b.f0, n * 4) == hipSuccess && hipMalloc(&b.f1, n * 4) == hipSuccess &&
+  b.log_cap = 2 * (int64_t)n + 1024;
+  bool ok = hipMalloc(&b.visited, words * 4) == hipSuccess &&
+            hipMalloc(&b.log, (size_t)b.log_cap * 4) == hipSuccess &&
             hipMalloc(&b.ctl, kBulkFindCtlWords * sizeof(unsigned)) == hipSuccess;
   if (!ok) {
     free_bulkfind(g);
-    cc_set_error("Bulk-Find scratch allocation (about 12 bytes per vertex) failed");
+    cc_set_error("Bulk-Find scratch allocation (about 8 bytes per vertex) failed");
     return CC_ENOMEM;
   }
   clear_bulkfind(g);
@@ -241,6 +243,21 @@ int launch_bulk_find_t(cc_graph* g, const int2* items, int64_t count, uint8_t* o
   HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device));
   int64_t grid = (2 * count + block - 1) / block;
   grid = std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(grid, cc::coop_limit(per_cu, cus)), 1024));
+  // level 0 takes one segment per block of the 2 * count endpoints
+  const int64_t seg0_cap = (2 * count + grid - 1) / grid;
+  if (seg0_cap * grid > g->bf_seg0_entries) {
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    (void)hipFree(g->bf.seg0);
+    g->bf.seg0 = nullptr;
+    g->bf_seg0_entries = 0;
+    if (hipMalloc(&g->bf.seg0, (size_t)(seg0_cap * grid) * 4) != hipSuccess) {
+      g->bf.seg0 = nullptr;
+      cc_set_error("Bulk-Find: hipMalloc of %lld level-0 entries failed", (long long)(seg0_cap * grid));
+      return CC_ENOMEM;
+    }
+    g->bf_seg0_entries = seg0_cap * grid;
+  }
+  g->bf.seg0_cap = seg0_cap;
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, g->stream, g->bf.ctl, kBulkFindCtlWords);
   HIP_TRY(hipGetLastError());
   int32_t* parent = g->parent;

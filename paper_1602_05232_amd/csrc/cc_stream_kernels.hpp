@@ -5,72 +5,15 @@
 // boundary per operation.  Meant for streams of many small minibatches,
 // whose cost in separate launches is mostly launch and drain latency.
 //
-// The grid is launched cooperatively (all blocks resident).  A barrier: the
-// block's threads meet at a workgroup barrier, then one thread per block
-// makes the block's writes visible device-wide (agent-scope release fence:
-// every wavefront of the block has passed the workgroup barrier, so one
-// fence covers them, as in the usual grid-sync construction), counts the
-// block in, and either publishes the next generation (last arrival) or
-// waits for it; it then drops stale cached lines (agent-scope acquire
-// fence) before the block's threads continue.  One fence pair per block
-// instead of one per wavefront: each fence writes back or invalidates the
-// whole L2 of the XCD, and thousands of them per barrier dominated its cost.
-// The arrival counter, the generation and the abort word sit on separate
-// 128-byte lines, so waiting blocks polling the generation do not contend
-// with arrivals.  Waiting is bounded: past the spin limit a block raises the
-// timeout flag and the abort word, and every block leaves the kernel at its
-// next barrier.
+// The grid is launched cooperatively; the barrier between operations is
+// grid_sync (cc_grid.hpp).
 #pragma once
 
+#include "cc_grid.hpp"
 #include "cc_kernels.hpp"
 
 namespace ccdev {
 namespace {
-
-// Barrier state: bar[0] arrivals (monotone within a launch), bar[32]
-// generation, bar[64] abort; all zero at launch.
-constexpr int kBarWords = 96;
-
-__device__ __forceinline__ unsigned bar_load(unsigned* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ bool grid_sync(unsigned* bar, unsigned& gen, int* flags, unsigned spin_limit) {
-  __shared__ int ok;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    const unsigned target = gen + 1;
-    int good = 1;
-    const unsigned arrived = __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
-    if (arrived == gridDim.x * target) {
-      __hip_atomic_store(bar + 32, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      unsigned spins = 0;
-      while (bar_load(bar + 32) < target) {
-        __builtin_amdgcn_s_sleep(2);
-        if ((++spins & 31u) == 0u) {
-          if (bar_load(bar + 64) != 0u) {
-            good = 0;
-            break;
-          }
-          if (spins > spin_limit) {
-            __hip_atomic_store(bar + 64, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            raise_flag(flags, kFlagTimeout);
-            good = 0;
-            break;
-          }
-        }
-      }
-    }
-    if (bar_load(bar + 64) != 0u) good = 0;
-    ok = good;
-    gen = target;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  }
-  __syncthreads();
-  return ok != 0;
-}
 
 template <class Ord>
 __global__ void k_stream(int32_t* __restrict__ parent, int64_t batches, const int2* __restrict__ edges,
@@ -115,10 +58,6 @@ __global__ void k_stream(int32_t* __restrict__ parent, int64_t batches, const in
     if (!grid_sync(bar, gen, flags, spin_limit)) break;
   }
   count_links(slots, links);
-}
-
-__global__ void k_zero_u32(unsigned* p, int count) {
-  for (int i = threadIdx.x; i < count; i += blockDim.x) p[i] = 0u;
 }
 
 }  // namespace
