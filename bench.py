@@ -120,6 +120,21 @@ def cpu_baseline(streams, budget_s: float):
             "update_edges": edges, "queries": queries, "seconds": dt}
 
 
+def parse_options(text: str) -> dict:
+    """Option overrides: a JSON object, or key=value pairs separated by commas
+    (integer values), e.g. find=1,hook=2."""
+    text = text.strip()
+    if not text:
+        return {}
+    if text.startswith("{"):
+        return json.loads(text)
+    out = {}
+    for part in text.split(","):
+        k, v = part.split("=", 1)
+        out[k.strip()] = int(v)
+    return out
+
+
 def result(value, steps, warmup, wall, config, dtype="int32"):
     return {"metric": METRIC, "value": value, "unit": "edges+queries/s", "n_gpus": 1, "steps": steps,
             "warmup": warmup, "ms_per_step": wall / max(1, steps) * 1e3, "higher_is_better": True,
@@ -142,7 +157,7 @@ def run_rmat(args):
     M, Qn, nb = len(s.edges), len(s.queries), s.num_batches
     opts = tuning.plain_options(s.n, workload="rmat")
     if args.options:
-        opts.update(json.loads(args.options))
+        opts.update(parse_options(args.options))
     E = torch.from_numpy(s.edges).cuda()
     Q = torch.from_numpy(s.queries).cuda()
     out = torch.empty(Qn, dtype=torch.uint8, device="cuda")
@@ -244,7 +259,7 @@ def run_grid(args):
     M, Qn, nb = len(s.edges), len(s.queries), s.num_batches
     opts = tuning.plain_options(s.n, workload="grid")
     if args.options:
-        opts.update(json.loads(args.options))
+        opts.update(parse_options(args.options))
     st = torch.cuda.Stream()
     with torch.cuda.stream(st):
         E = torch.from_numpy(s.edges).cuda()
@@ -349,7 +364,7 @@ def run_batched(args):
     popts = tuning.lookup("pool", "mixed", int(np.median(ns))) or {}
     popts = {k: v for k, v in popts.items() if k not in ("update_mode", "compress_every")}
     if args.options:
-        popts.update(json.loads(args.options))
+        popts.update(parse_options(args.options))
     pool = ccgpu.Pool(int(ns.sum()), G, **popts)
     ids = [pool.add(s.n) for s in streams]
     ops_per_step = []
@@ -644,7 +659,7 @@ def main():
     ap.add_argument("--serve-scale", type=int, default=22, help="R-MAT scale of each served graph")
     ap.add_argument("--scale", type=int, default=24, help="R-MAT scale of the rmat24 workload")
     ap.add_argument("--graphs", type=int, default=1024, help="graphs of the batched workload")
-    ap.add_argument("--options", default="", help="JSON dict of option overrides")
+    ap.add_argument("--options", default="", help="option overrides: JSON object or key=value,key=value")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
