@@ -242,7 +242,8 @@ int launch_bulk_find_t(cc_graph* g, const int2* items, int64_t count, uint8_t* o
   HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bulk_find<KIND, Ord>, block, 0));
   HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device));
   int64_t grid = (2 * count + block - 1) / block;
-  grid = std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(grid, cc::coop_limit(per_cu, cus)), 1024));
+  grid = std::min<int64_t>(std::min<int64_t>(grid, cc::coop_limit(per_cu, cus)), 1024);
+  grid = std::max<int64_t>(1, std::min<int64_t>(grid, (int64_t)g->tune.grid_cap));
   // level 0 takes one segment per block of the 2 * count endpoints
   const int64_t seg0_cap = (2 * count + grid - 1) / grid;
   if (seg0_cap * grid > g->bf_seg0_entries) {

@@ -27,6 +27,8 @@ OPTION_SETS = [
     dict(update_mode=2),
     dict(update_mode=2, hook=1, grid_cap=3),
     dict(update_mode=2, query_halving=0, compress_every=2),
+    dict(find=1, grid_cap=3),
+    dict(find=1, hook=1, grid_cap=16),
     dict(find=1),
     dict(find=1, hook=2),
 ]
@@ -155,7 +157,8 @@ def test_edge_cases(cc, mode):
 
 
 @pytest.mark.parametrize("opts", [dict(update_mode=0), dict(update_mode=1), dict(update_mode=0, hook=1),
-                                  dict(update_mode=0, hook=2), dict(update_mode=2), dict(update_mode=2, hook=1)],
+                                  dict(update_mode=0, hook=2), dict(update_mode=2), dict(update_mode=2, hook=1),
+                                  dict(find=1), dict(find=1, hook=2)],
                          ids=opt_id)
 def test_deep_chain(cc, opts):
     # reversed path in one minibatch, then in single-edge minibatches
@@ -288,6 +291,24 @@ def test_bulk_find_worked_example(cc):
     assert after[5] == 5 and after[19] == 19
     assert g.sync() == cc.cc.CC_OK
     g.close()
+
+
+@pytest.mark.parametrize("opts", [dict(find=1), dict(find=1, grid_cap=5), dict(find=1, hook=2, grid_cap=64)],
+                         ids=opt_id)
+def test_bulk_find_wide_levels(cc, opts):
+    """Minibatches large enough that Bulk-Find's levels are appended in
+    per-block chunks (more than blockDim.x entries per block), on forests
+    deep enough to need several levels: a long path split over the batches
+    plus uniform random edges."""
+    n = 1 << 20
+    rng = np.random.default_rng(7)
+    path = np.stack([np.arange(n - 1), np.arange(1, n)], 1).astype(np.int32)[rng.permutation(n - 1)]
+    rand = synth.uniform_pairs(synth.key(29, 0, 1), 0, 1 << 20, n)
+    edges = np.concatenate([path[: n // 2], rand, path[n // 2:]])
+    sizes = [1 << 18, 1 << 19, 1 << 20, len(edges) - (1 << 18) - (1 << 19) - (1 << 20)]
+    q = synth.uniform_pairs(synth.key(29, 0, 2), 0, (1 << 19) * len(sizes), n)
+    s = synth.Stream("wide", n, edges, synth._offsets(sizes), q, synth._offsets([1 << 19] * len(sizes)))
+    run_parity(cc, s, opts)
 
 
 def test_bulk_find_compresses_every_endpoint(cc):
