@@ -64,10 +64,10 @@ def source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel_tag: str):
-    """HBM traffic per launch from the committed counter summary, if it was
-    taken on the current kernel sources."""
-    p = os.path.join(ROOT, "profiles", "pmc_%s.txt" % kernel_tag)
+def load_counter(file_tag: str, key: str):
+    """A figure from a committed counter summary (profiles/pmc_<tag>.txt), if
+    the counters were taken on the current kernel sources."""
+    p = os.path.join(ROOT, "profiles", "pmc_%s.txt" % file_tag)
     if not os.path.exists(p):
         return None
     kv = {}
@@ -78,9 +78,14 @@ def load_traffic(kernel_tag: str):
     if kv.get("source_digest") != source_digest():
         return None
     try:
-        return float(kv["traffic_bytes_per_launch"])
+        return float(kv[key])
     except (KeyError, ValueError):
         return None
+
+
+def load_traffic(kernel_tag: str):
+    """HBM traffic per launch (FETCH_SIZE + WRITE_SIZE, calibrated)."""
+    return load_counter(kernel_tag, "traffic_bytes_per_launch")
 
 
 def pct(xs, p):
@@ -89,6 +94,23 @@ def pct(xs, p):
         return None
     k = min(len(xs) - 1, max(0, int(round(p / 100.0 * (len(xs) - 1)))))
     return xs[k]
+
+
+def host_info() -> dict:
+    """The host the CPU baseline ran on: model name, clock, logical CPUs."""
+    info = {"nproc": os.cpu_count()}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                k, _, v = line.partition(":")
+                k = k.strip()
+                if k == "model name" and "model" not in info:
+                    info["model"] = v.strip()
+                elif k == "cpu MHz" and "mhz" not in info:
+                    info["mhz"] = float(v)
+    except OSError:
+        pass
+    return info
 
 
 def cpu_baseline(streams, budget_s: float):
@@ -117,7 +139,7 @@ def cpu_baseline(streams, budget_s: float):
         what += "; ... %d streams in all" % len(done)
     return {"value": (edges + queries) / dt, "unit": "edges+queries/s", "cores": 1, "kind": "oracle",
             "sample": "%s, each with its query batches (%d edges, %d queries, %.1f s)" % (what, edges, queries, dt),
-            "update_edges": edges, "queries": queries, "seconds": dt}
+            "update_edges": edges, "queries": queries, "seconds": dt, "host": host_info()}
 
 
 def parse_options(text: str) -> dict:
@@ -219,6 +241,7 @@ def run_rmat(args):
                            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                            "traffic_rate_GBs": None if traffic is None else
                            traffic * nb * steps / sum(upd_t) / 1e9,
+                           "l2_hit_rate": load_counter("l2_" + tag, "l2_hit_rate"),
                            "kernel": "k_update_fused" if fused else "k_filter+k_link_live+k_compress_live",
                            "bytes_per_edge": UPDATE_BYTES_PER_EDGE,
                            "avg_update_ms": sum(upd_t) / (steps * nb) * 1e3,
@@ -227,10 +250,17 @@ def run_rmat(args):
         torch.cuda.empty_cache()
         G = roofline.gather_rate(s.n)
         Gbig = roofline.gather_rate(1 << 30, count=1 << 27)
+        Gsmall = {"2^16": roofline.gather_rate(1 << 16), "2^22": roofline.gather_rate(1 << 22)}
         Bs = roofline.stream_bandwidth()
+        C = roofline.cas_rate(s.n)
         Eroof = roofline.edge_roofline(G, Bs)
+        links = s.n - c
         res["gather_roofline"] = {
-            "G_gathers_per_s_table_n": G, "G_gathers_per_s_table_2^30": Gbig, "stream_read_GBs": Bs / 1e9,
+            "G_gathers_per_s_table_n": G, "G_gathers_per_s_table_2^30": Gbig,
+            "G_gathers_per_s_table_2^16": Gsmall["2^16"], "G_gathers_per_s_table_2^22": Gsmall["2^22"],
+            "C_cas_per_s_table_n": C, "links_per_step": links,
+            "links_per_s_in_update": links * steps / sum(upd_t),
+            "stream_read_GBs": Bs / 1e9,
             "E_roof_edges_per_s": Eroof, "frac": upd_rate / Eroof,
             "E_roof_beyond_cache_edges_per_s": roofline.edge_roofline(Gbig, Bs),
             "query_roof_per_s": G / 2.0, "query_frac": qry_rate / (G / 2.0),
