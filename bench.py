@@ -633,7 +633,8 @@ def run_bigbatch(args):
 
 def run_components(args):
     """Number of components against the fraction of the stream consumed, for
-    each workload shape at n = 2^24 (the measurement behind Fig. 2)."""
+    each workload shape at n = 2^k (k = --components-log2n, default 24; the
+    measurement behind Fig. 2, whose streams have about 10^8 vertices)."""
     import numpy as np
     import torch
 
@@ -641,18 +642,23 @@ def run_components(args):
     import paper_1602_05232_amd as ccgpu
     from paper_1602_05232_amd import tuning
 
+    k = args.components_log2n
+    if k % 3 or not 12 <= k <= 27:
+        raise SystemExit("--components-log2n must be a multiple of 3 in [12, 27] (the 3-D mesh is 2^(k/3) a side)")
+    n, L = 1 << k, 1 << (k // 3)
     shapes = {
-        "random (ER, 5 edges/vertex)": lambda: synth.er_stream(n=1 << 24, batches=80, batch=(5 << 24) // 80,
+        "random (ER, 5 edges/vertex)": lambda: synth.er_stream(n=n, batches=80, batch=(5 * n) // 80,
                                                                qbatch=1, probes=0),
-        "rmat (scale 24, EF 16)": lambda: synth.rmat_stream(scale=24, qbatch=1, probes=0),
-        "grid3d (256^3)": lambda: synth.grid3d_stream_cfg(L=256, batch=1 << 21, qbatch=1, probes=0),
-        "local5 (window 2^12)": lambda: synth.local_stream(n=1 << 24, degree=5, window=1 << 12, batch=1 << 21,
+        "rmat (scale %d, EF 16)" % k: lambda: synth.rmat_stream(scale=k, qbatch=1, probes=0),
+        "grid3d (%d^3)" % L: lambda: synth.grid3d_stream_cfg(L=L, batch=1 << 21, qbatch=1, probes=0),
+        "local5 (window 2^12)": lambda: synth.local_stream(n=n, degree=5, window=1 << 12, batch=1 << 21,
                                                            qbatch=1, probes=0),
-        "local16 (window 2^12)": lambda: synth.local_stream(n=1 << 24, degree=16, window=1 << 12,
+        "local16 (window 2^12)": lambda: synth.local_stream(n=n, degree=16, window=1 << 12,
                                                             batch=1 << 22, qbatch=1, probes=0),
     }
     traces, total_t, total_e = {}, 0.0, 0
     for name, make in shapes.items():
+        log("generating %s" % name)
         s = make()
         E = torch.from_numpy(s.edges).cuda()
         g = ccgpu.Graph(s.n, **tuning.plain_options(s.n, "rmat"))
@@ -669,9 +675,9 @@ def run_components(args):
         traces[name] = pts
         log("%s: %d edges, components at end %d" % (name, len(s.edges), pts[-1][1]))
         g.close()
-        del E
+        del E, s
         torch.cuda.empty_cache()
-    res = result(total_e / total_t, 1, 0, total_t, {"workload": "component-trace", "n": 1 << 24,
+    res = result(total_e / total_t, 1, 0, total_t, {"workload": "component-trace", "n": n,
                                                       "shapes": list(shapes)})
     res["unit"] = "edges/s (one count read per minibatch)"
     res["traces"] = traces
@@ -689,6 +695,7 @@ def main():
     ap.add_argument("--serve-scale", type=int, default=22, help="R-MAT scale of each served graph")
     ap.add_argument("--scale", type=int, default=24, help="R-MAT scale of the rmat24 workload")
     ap.add_argument("--graphs", type=int, default=1024, help="graphs of the batched workload")
+    ap.add_argument("--components-log2n", type=int, default=24, help="log2 of n for the components workload")
     ap.add_argument("--options", default="", help="option overrides: JSON object or key=value,key=value")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
