@@ -92,6 +92,10 @@ BENCH_SIGNATURES = {
     "ccb_stream_read": (_i32, [_vp, _i64, _vp, _vp]),
     "ccb_copy": (_i32, [_vp, _vp, _i64, _vp]),
     "ccb_cas": (_i32, [_vp, _i64, _i64, ctypes.c_uint32, _vp]),
+    "ccb_event_create": (_i32, [_vp]),
+    "ccb_event_record": (_i32, [_vp, _vp]),
+    "ccb_event_elapsed_ms": (_i32, [_vp, _vp, _vp]),
+    "ccb_event_destroy": (_i32, [_vp]),
 }
 
 

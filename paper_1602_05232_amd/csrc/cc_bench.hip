@@ -116,3 +116,27 @@ extern "C" int ccb_cas(int32_t* table, int64_t n_table, int64_t count, uint32_t 
                      (uint32_t)(n_table - 1), count, seed);
   return launched();
 }
+
+extern "C" int ccb_event_create(void** ev) {
+  if (!ev) return -1;
+  hipEvent_t e = nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return -4;
+  *ev = (void*)e;
+  return 0;
+}
+
+extern "C" int ccb_event_record(void* ev, void* stream) {
+  if (!ev) return -1;
+  return hipEventRecord((hipEvent_t)ev, (hipStream_t)stream) == hipSuccess ? 0 : -4;
+}
+
+extern "C" int ccb_event_elapsed_ms(void* start, void* stop, float* ms) {
+  if (!start || !stop || !ms) return -1;
+  if (hipEventSynchronize((hipEvent_t)stop) != hipSuccess) return -4;
+  return hipEventElapsedTime(ms, (hipEvent_t)start, (hipEvent_t)stop) == hipSuccess ? 0 : -4;
+}
+
+extern "C" int ccb_event_destroy(void* ev) {
+  if (!ev) return -1;
+  return hipEventDestroy((hipEvent_t)ev) == hipSuccess ? 0 : -4;
+}

@@ -10,6 +10,8 @@ parent reads (one find per endpoint at depth one) plus 8 streamed bytes.
 """
 from __future__ import annotations
 
+import ctypes
+
 import torch
 
 from .cc import lib, stream_handle
@@ -60,6 +62,36 @@ def cas_rate(n_table: int, count: int = 1 << 26) -> float:
     def run():
         assert lib().ccb_cas(t.data_ptr(), n_table, count, 0x7654321, h) == 0
     return count / _time(run)
+
+
+class TimingEvent:
+    """A HIP event for timing only (created by ccb_event_create, without the
+    system-scope fence of a default event), recorded on a torch stream.
+    elapsed_time(stop) returns milliseconds, as torch.cuda.Event does."""
+
+    def __init__(self):
+        h = ctypes.c_void_p()
+        rc = lib().ccb_event_create(ctypes.byref(h))
+        if rc != 0:
+            raise RuntimeError("ccb_event_create failed (%d)" % rc)
+        self.handle = h.value
+
+    def record(self, stream=None):
+        rc = lib().ccb_event_record(self.handle, stream_handle(stream))
+        if rc != 0:
+            raise RuntimeError("ccb_event_record failed (%d)" % rc)
+
+    def elapsed_time(self, stop: "TimingEvent") -> float:
+        ms = ctypes.c_float()
+        rc = lib().ccb_event_elapsed_ms(self.handle, stop.handle, ctypes.byref(ms))
+        if rc != 0:
+            raise RuntimeError("ccb_event_elapsed_ms failed (%d)" % rc)
+        return ms.value
+
+    def __del__(self):
+        h, self.handle = getattr(self, "handle", None), None
+        if h:
+            lib().ccb_event_destroy(h)
 
 
 def copy_bytes(dst: torch.Tensor, src: torch.Tensor, nbytes: int):
