@@ -415,8 +415,17 @@ def run_batched(args):
             pool.run(ops)
         return pool.sync()
 
+    # The per-graph baseline runs with its own best options: a short trial of
+    # each candidate set (one step each), then the fastest is timed.
+    candidates = [dict(), dict(hook=2, compress_linked=0), dict(hook=1, compress_linked=0),
+                  dict(hook=2, compress_linked=0, block=1024)]
     graphs = [ccgpu.Graph(s.n) for s in streams]
     out_plain = torch.empty_like(out)
+
+    def set_plain_options(o):
+        for gr in graphs:
+            for k, v in {**dict(hook=0, compress_linked=1, block=256), **o}.items():
+                gr.set_option(k, v)
 
     def plain_step():
         for gr in graphs:
@@ -439,6 +448,16 @@ def run_batched(args):
         torch.cuda.synchronize()
         return time.perf_counter() - t0
 
+    trial = []
+    for o in candidates:
+        set_plain_options(o)
+        plain_step()
+        t0 = time.perf_counter()
+        plain_step()
+        trial.append((time.perf_counter() - t0, o))
+        log("per-graph trial %s: %.1f ms" % (o, trial[-1][0] * 1e3))
+    plain_opts = min(trial, key=lambda x: x[0])[1]
+    set_plain_options(plain_opts)
     wall_plain = timed(plain_step, "per-graph")
     wall_pool = timed(pool_step, "pool")
     assert torch.equal(out, out_plain), "pool answers differ from per-graph answers"
@@ -466,6 +485,8 @@ def run_batched(args):
         "edges": M, "queries": Qn, "steps_per_graph": 4, "queries_per_step": 1 << 12,
         "n_distribution": "clip(round(2^X), 2^10, 2^20), X ~ N(14, 2)", "form": "pool", "options": popts})
     res.update({"plain_value": steps * (M + Qn) / wall_plain, "plain_ms_per_step": wall_plain / steps * 1e3,
+                "plain_options": plain_opts,
+                "plain_trials_ms": [{"options": o, "ms": t * 1e3} for t, o in trial],
                 "speedup_vs_plain": wall_plain / wall_pool, "components": comps,
                 "one_launch": {"value": steps * (M + Qn) / wall_one, "ms_per_step": wall_one / steps * 1e3,
                                "speedup_vs_plain": wall_plain / wall_one,
@@ -514,6 +535,8 @@ def run_serve(args):
     popts = tuning.lookup("pool", "mixed", n) or {}
     popts = {k: v for k, v in popts.items() if k not in ("update_mode", "compress_every")}
     popts["compress_linked"] = 0  # rounds overlap on two streams
+    if popts.get("hook") == 2 and S * n > (1 << 27):
+        popts["hook"] = 1  # rank bits need arena ids below 2^27; 64 resident graphs exceed that
 
     def with_arrivals(times):
         out = []

@@ -81,7 +81,7 @@ def tune_plain(stream, workload, reps=3, quick=False, log=print):
 
 def pool_candidates(quick=False):
     out = [dict(block=b, items=i, hook=h, compress_linked=c)
-           for b, i, h, c in itertools.product((256, 512, 1024), (0, 4, 8), (0, 1), (0, 1))]
+           for b, i, h, c in itertools.product((256, 512, 1024), (0, 4, 8), (0, 1, 2), (0, 1))]
     return out[::5] if quick else out
 
 

@@ -147,11 +147,11 @@ int reserve_meta(RingSlot* s, int64_t words) {
   return CC_OK;
 }
 
-template <int ITEMS, bool HASH, bool HALVE>
+template <int ITEMS, int HOOK, bool HALVE>
 int launch_rounds_t(cc_pool* p, const RingSlot* s, int rounds, uint32_t max_tiles) {
   const int B = p->tune.block;
   int per_cu = 0, cus = 0;
-  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pool_rounds<ITEMS, HASH, HALVE>, B, 0));
+  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pool_rounds<ITEMS, HOOK, HALVE>, B, 0));
   HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device));
   int64_t grid = std::min<int64_t>(std::min<int64_t>(max_tiles, cc::coop_limit(per_cu, cus)), p->tune.grid_cap);
   grid = std::max<int64_t>(grid, 1);
@@ -166,18 +166,24 @@ int launch_rounds_t(cc_pool* p, const RingSlot* s, int rounds, uint32_t max_tile
   unsigned* bar = p->bar;
   unsigned spin = (unsigned)p->tune.spin_limit;
   void* args[] = {&ops, &rstart, &rtiles, &rounds, &arena, &glinks, &flags, &bar, &spin};
-  HIP_TRY(hipLaunchCooperativeKernel((const void*)k_pool_rounds<ITEMS, HASH, HALVE>, dim3((unsigned)grid), dim3(B),
+  HIP_TRY(hipLaunchCooperativeKernel((const void*)k_pool_rounds<ITEMS, HOOK, HALVE>, dim3((unsigned)grid), dim3(B),
                                      args, 0, p->stream));
   return CC_OK;
 }
 
+template <int ITEMS, int HOOK>
+int launch_rounds_h(cc_pool* p, const RingSlot* s, int rounds, uint32_t max_tiles) {
+  return p->tune.query_halving ? launch_rounds_t<ITEMS, HOOK, true>(p, s, rounds, max_tiles)
+                               : launch_rounds_t<ITEMS, HOOK, false>(p, s, rounds, max_tiles);
+}
+
 template <int ITEMS>
 int launch_rounds_i(cc_pool* p, const RingSlot* s, int rounds, uint32_t max_tiles) {
-  const bool hash = p->tune.hook == 1, halve = p->tune.query_halving != 0;
-  if (hash) return halve ? launch_rounds_t<ITEMS, true, true>(p, s, rounds, max_tiles)
-                         : launch_rounds_t<ITEMS, true, false>(p, s, rounds, max_tiles);
-  return halve ? launch_rounds_t<ITEMS, false, true>(p, s, rounds, max_tiles)
-               : launch_rounds_t<ITEMS, false, false>(p, s, rounds, max_tiles);
+  switch (p->tune.hook) {
+    case 1: return launch_rounds_h<ITEMS, 1>(p, s, rounds, max_tiles);
+    case 2: return launch_rounds_h<ITEMS, 2>(p, s, rounds, max_tiles);
+    default: return launch_rounds_h<ITEMS, 0>(p, s, rounds, max_tiles);
+  }
 }
 
 int launch_rounds(cc_pool* p, const RingSlot* s, int items, int rounds, uint32_t max_tiles) {
@@ -189,27 +195,30 @@ int launch_rounds(cc_pool* p, const RingSlot* s, int items, int rounds, uint32_t
   }
 }
 
-template <int ITEMS, bool HASH, bool RECORD>
+template <int ITEMS, int HOOK, bool RECORD>
 void launch_phase_t(cc_pool* p, const RingSlot* s, const OpDesc* d, int nops, uint32_t ntiles) {
   const int B = p->tune.block;
   const unsigned grid = (unsigned)std::min<int64_t>(ntiles, p->tune.grid_cap);
   if (p->tune.query_halving)
-    hipLaunchKernelGGL((k_pool_phase<ITEMS, HASH, RECORD, true>), dim3(grid), dim3(B), 0, p->stream, d, nops,
+    hipLaunchKernelGGL((k_pool_phase<ITEMS, HOOK, RECORD, true>), dim3(grid), dim3(B), 0, p->stream, d, nops,
                        ntiles, p->arena, p->glinks, p->flags, s->hooked, s->ctl);
   else
-    hipLaunchKernelGGL((k_pool_phase<ITEMS, HASH, RECORD, false>), dim3(grid), dim3(B), 0, p->stream, d, nops,
+    hipLaunchKernelGGL((k_pool_phase<ITEMS, HOOK, RECORD, false>), dim3(grid), dim3(B), 0, p->stream, d, nops,
                        ntiles, p->arena, p->glinks, p->flags, s->hooked, s->ctl);
+}
+
+template <int ITEMS, int HOOK>
+void launch_phase_h(cc_pool* p, const RingSlot* s, const OpDesc* d, int nops, uint32_t ntiles, bool record) {
+  if (record) launch_phase_t<ITEMS, HOOK, true>(p, s, d, nops, ntiles);
+  else launch_phase_t<ITEMS, HOOK, false>(p, s, d, nops, ntiles);
 }
 
 template <int ITEMS>
 void launch_phase_i(cc_pool* p, const RingSlot* s, const OpDesc* d, int nops, uint32_t ntiles, bool record) {
-  const bool hash = p->tune.hook == 1;
-  if (hash) {
-    if (record) launch_phase_t<ITEMS, true, true>(p, s, d, nops, ntiles);
-    else launch_phase_t<ITEMS, true, false>(p, s, d, nops, ntiles);
-  } else {
-    if (record) launch_phase_t<ITEMS, false, true>(p, s, d, nops, ntiles);
-    else launch_phase_t<ITEMS, false, false>(p, s, d, nops, ntiles);
+  switch (p->tune.hook) {
+    case 1: launch_phase_h<ITEMS, 1>(p, s, d, nops, ntiles, record); break;
+    case 2: launch_phase_h<ITEMS, 2>(p, s, d, nops, ntiles, record); break;
+    default: launch_phase_h<ITEMS, 0>(p, s, d, nops, ntiles, record); break;
   }
 }
 
@@ -294,8 +303,8 @@ extern "C" int cc_pool_set_option(cc_pool* p, int key, int64_t value) {
     cc_set_error("cc_pool_set_option: option %d does not apply to pools", key);
     return CC_EINVAL;
   }
-  if (key == CC_OPT_HOOK && value == 2) {
-    cc_set_error("cc_pool_set_option: union by rank is not available in pools");
+  if (key == CC_OPT_HOOK && value == 2 && p->capacity > (int64_t)kIdMask + 1) {
+    cc_set_error("cc_pool_set_option: union by rank needs a capacity of at most 2^%d vertices", kRankShift);
     return CC_EINVAL;
   }
   if (key == CC_OPT_HOOK) {
@@ -503,9 +512,15 @@ extern "C" int cc_pool_run(cc_pool* p, const cc_op* ops, int32_t num_ops) {
     const bool record = rupd[(size_t)r] && p->tune.compress_linked;
     launch_phase(p, slot, ritem_per_thread[(size_t)r], slot->dev + rstart[(size_t)r], (int)rcount[(size_t)r],
                  rtiles[(size_t)r], record);
-    if (record)
-      hipLaunchKernelGGL(k_compress_hooked, dim3(1024), dim3(256), 0, p->stream, p->arena, slot->hooked,
-                         slot->ctl, (int32_t)std::min<int64_t>(p->capacity, 0x7fffffff), p->flags);
+    if (record) {
+      const int32_t cap = (int32_t)std::min<int64_t>(p->capacity, 0x7fffffff);
+      if (p->tune.hook == 2)
+        hipLaunchKernelGGL(k_compress_hooked<true>, dim3(1024), dim3(256), 0, p->stream, p->arena, slot->hooked,
+                           slot->ctl, cap, p->flags);
+      else
+        hipLaunchKernelGGL(k_compress_hooked<false>, dim3(1024), dim3(256), 0, p->stream, p->arena, slot->hooked,
+                           slot->ctl, cap, p->flags);
+    }
   }
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipEventRecord(slot->done, p->stream));
@@ -521,8 +536,15 @@ extern "C" int cc_pool_labels(cc_pool* p, int32_t id, int32_t* out) {
   const int32_t base = (int32_t)g.base, n = (int32_t)g.n;
   if (p->tune.hook == 1) {
     hipLaunchKernelGGL(k_iota_i32, dim3(blocks), dim3(256), 0, p->stream, out, n);
-    hipLaunchKernelGGL(k_pool_labels_min, dim3(blocks), dim3(256), 0, p->stream, p->arena, base, n, out, p->flags);
-    hipLaunchKernelGGL(k_pool_labels_gather, dim3(blocks), dim3(256), 0, p->stream, p->arena, base, n, out,
+    hipLaunchKernelGGL(k_pool_labels_min<false>, dim3(blocks), dim3(256), 0, p->stream, p->arena, base, n, out,
+                       p->flags);
+    hipLaunchKernelGGL(k_pool_labels_gather<false>, dim3(blocks), dim3(256), 0, p->stream, p->arena, base, n, out,
+                       p->flags);
+  } else if (p->tune.hook == 2) {
+    hipLaunchKernelGGL(k_iota_i32, dim3(blocks), dim3(256), 0, p->stream, out, n);
+    hipLaunchKernelGGL(k_pool_labels_min<true>, dim3(blocks), dim3(256), 0, p->stream, p->arena, base, n, out,
+                       p->flags);
+    hipLaunchKernelGGL(k_pool_labels_gather<true>, dim3(blocks), dim3(256), 0, p->stream, p->arena, base, n, out,
                        p->flags);
   } else {
     hipLaunchKernelGGL(k_pool_labels_id, dim3(blocks), dim3(256), 0, p->stream, p->arena, base, n, out, p->flags);
@@ -624,25 +646,36 @@ extern "C" int cc_pool_load(cc_pool* p, int32_t id, const void* host_buf) {
     cc_set_error("cc_pool_load: image has n=%lld, graph has n=%lld", (long long)hdr[0], (long long)g.n);
     return CC_EINVAL;
   }
+  if (p->tune.hook == 2) {
+    // a rank image keeps ranks, not the order, in its words: walk it on the host
+    int64_t roots = 0;
+    if (!cc::check_forest(reinterpret_cast<const int32_t*>((const char*)host_buf + 16), g.n, 2, &roots) ||
+        hdr[1] != g.n - roots) {
+      cc_set_error("cc_pool_load: image is not a forest");
+      return CC_ECORRUPT;
+    }
+  }
   int rc = ensure_staging(p, g.n);
   if (rc != CC_OK) return rc;
   const unsigned blocks = blocks_for(g.n, 256, 4096);
   HIP_TRY(hipMemcpyAsync(p->staging, (const char*)host_buf + 16, (size_t)g.n * 4, hipMemcpyHostToDevice,
                          p->stream));
-  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, p->stream, p->check, 2);
-  if (p->tune.hook == 1)
-    hipLaunchKernelGGL(k_check_image<true>, dim3(blocks), dim3(256), 0, p->stream, p->staging, (int32_t)g.n,
-                       p->check);
-  else
-    hipLaunchKernelGGL(k_check_image<false>, dim3(blocks), dim3(256), 0, p->stream, p->staging, (int32_t)g.n,
-                       p->check);
-  HIP_TRY(hipGetLastError());
-  unsigned long long res[2] = {0, 0};
-  HIP_TRY(hipMemcpyAsync(res, p->check, 16, hipMemcpyDeviceToHost, p->stream));
-  HIP_TRY(hipStreamSynchronize(p->stream));
-  if (res[0] != 0 || hdr[1] != g.n - (int64_t)res[1]) {
-    cc_set_error("cc_pool_load: image is not a forest under the pool's linking order");
-    return CC_ECORRUPT;
+  if (p->tune.hook != 2) {
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, p->stream, p->check, 2);
+    if (p->tune.hook == 1)
+      hipLaunchKernelGGL(k_check_image<true>, dim3(blocks), dim3(256), 0, p->stream, p->staging, (int32_t)g.n,
+                         p->check);
+    else
+      hipLaunchKernelGGL(k_check_image<false>, dim3(blocks), dim3(256), 0, p->stream, p->staging, (int32_t)g.n,
+                         p->check);
+    HIP_TRY(hipGetLastError());
+    unsigned long long res[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(res, p->check, 16, hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    if (res[0] != 0 || hdr[1] != g.n - (int64_t)res[1]) {
+      cc_set_error("cc_pool_load: image is not a forest under the pool's linking order");
+      return CC_ECORRUPT;
+    }
   }
   unsigned long long links = (unsigned long long)hdr[1];
   hipLaunchKernelGGL(k_place, dim3(blocks), dim3(256), 0, p->stream, p->staging, (int32_t)g.base, (int32_t)g.n,

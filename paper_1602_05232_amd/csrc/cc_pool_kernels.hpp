@@ -52,11 +52,15 @@ __device__ __forceinline__ int block_sum(int v, int* red) {
 }
 
 // One tile of one operation (block-uniform: every thread of the block calls it).
-template <int ITEMS, bool HASH, bool RECORD, bool HALVE_Q>
+// HOOK: 0 id order, 1 hashed priority (of graph-local ids), 2 union by rank
+// (arena ids keep each graph's local order, so ties break as in a lone graph;
+// the rank bits need arena ids below 2^kRankShift).
+template <int ITEMS, int HOOK, bool RECORD, bool HALVE_Q>
 __device__ __forceinline__ void pool_tile(const OpDesc& op, uint32_t t, int32_t* __restrict__ arena,
                                           unsigned long long* __restrict__ glinks, int* __restrict__ flags,
                                           int32_t* __restrict__ hooked, unsigned* __restrict__ hooked_ctl,
                                           int* wave_off, unsigned* blk, int* red) {
+  constexpr bool R = HOOK == 2;
   const uint32_t T = blockDim.x * ITEMS;
   const int64_t t0 = (int64_t)(t - op.tile0) * T;
   int2 e[ITEMS];
@@ -77,15 +81,17 @@ __device__ __forceinline__ void pool_tile(const OpDesc& op, uint32_t t, int32_t*
       }
       if (e[k].x == e[k].y) continue;
       const int32_t u = op.base + e[k].x, v = op.base + e[k].y;
-      const int32_t pu = ld(arena + u), pv = ld(arena + v);
+      const int32_t pu = ldp<R>(arena + u), pv = ldp<R>(arena + v);
       if (pu == pv || pu == v || pv == u) continue;
-      const int32_t ru = find_halve_from(arena, u, pu, op.n, flags);
-      const int32_t rv = find_halve_from(arena, v, pv, op.n, flags);
+      const int32_t ru = find_halve_from<R>(arena, u, pu, op.n, flags);
+      const int32_t rv = find_halve_from<R>(arena, v, pv, op.n, flags);
       if (ru != rv) {
-        if (HASH) {
+        if (HOOK == 1) {
           ByHash o;
           o.base = op.base;
           hk[k] = link_roots(arena, ru, rv, op.n, flags, o);
+        } else if (HOOK == 2) {
+          hk[k] = link_roots_rank(arena, ru, rv, op.n, flags);
         } else {
           hk[k] = link_roots(arena, ru, rv, op.n, flags, ById{});
         }
@@ -111,8 +117,8 @@ __device__ __forceinline__ void pool_tile(const OpDesc& op, uint32_t t, int32_t*
       } else if (e[k].x == e[k].y) {
         a = 1;
       } else {
-        const int32_t ru = find_root<HALVE_Q>(arena, op.base + e[k].x, op.n, flags);
-        const int32_t rv = find_root<HALVE_Q>(arena, op.base + e[k].y, op.n, flags);
+        const int32_t ru = find_root<HALVE_Q, R>(arena, op.base + e[k].x, op.n, flags);
+        const int32_t rv = find_root<HALVE_Q, R>(arena, op.base + e[k].y, op.n, flags);
         a = ru == rv;
       }
       if (i < op.count) op.out[i] = a;
@@ -120,7 +126,7 @@ __device__ __forceinline__ void pool_tile(const OpDesc& op, uint32_t t, int32_t*
   }
 }
 
-template <int ITEMS, bool HASH, bool RECORD, bool HALVE_Q>
+template <int ITEMS, int HOOK, bool RECORD, bool HALVE_Q>
 __global__ void k_pool_phase(const OpDesc* __restrict__ ops, int nops, uint32_t ntiles,
                              int32_t* __restrict__ arena, unsigned long long* __restrict__ glinks,
                              int* __restrict__ flags, int32_t* __restrict__ hooked,
@@ -130,7 +136,7 @@ __global__ void k_pool_phase(const OpDesc* __restrict__ ops, int nops, uint32_t 
   __shared__ int red[16];
   for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const OpDesc op = ops[find_op(ops, nops, t)];
-    pool_tile<ITEMS, HASH, RECORD, HALVE_Q>(op, t, arena, glinks, flags, hooked, hooked_ctl, wave_off, blk, red);
+    pool_tile<ITEMS, HOOK, RECORD, HALVE_Q>(op, t, arena, glinks, flags, hooked, hooked_ctl, wave_off, blk, red);
   }
 }
 
@@ -138,7 +144,7 @@ __global__ void k_pool_phase(const OpDesc* __restrict__ ops, int nops, uint32_t 
 // [rstart[r], rstart[r+1]) and rtiles[r] tiles; device-wide barriers keep the
 // rounds in order (an operation of round r+1 may depend on one of round r on
 // the same graph).  No linked-root recording in this form.
-template <int ITEMS, bool HASH, bool HALVE_Q>
+template <int ITEMS, int HOOK, bool HALVE_Q>
 __global__ void k_pool_rounds(const OpDesc* __restrict__ ops, const int32_t* __restrict__ rstart,
                               const uint32_t* __restrict__ rtiles, int nrounds, int32_t* __restrict__ arena,
                               unsigned long long* __restrict__ glinks, int* __restrict__ flags, unsigned* bar,
@@ -153,7 +159,7 @@ __global__ void k_pool_rounds(const OpDesc* __restrict__ ops, const int32_t* __r
     const uint32_t ntiles = rtiles[r];
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
       const OpDesc op = ro[find_op(ro, nops, t)];
-      pool_tile<ITEMS, HASH, false, HALVE_Q>(op, t, arena, glinks, flags, nullptr, nullptr, wave_off, blk, red);
+      pool_tile<ITEMS, HOOK, false, HALVE_Q>(op, t, arena, glinks, flags, nullptr, nullptr, wave_off, blk, red);
     }
     if (r + 1 < nrounds && !grid_sync(bar, gen, flags, spin_limit)) break;
   }
@@ -174,28 +180,33 @@ __global__ void k_pool_labels_id(int32_t* __restrict__ arena, int32_t base, int3
   }
 }
 
-// Hashed order: minimum id per root (out pre-filled with out[v] = v, so a
-// root needs no atomic), then a gather.
+// Hashed order or rank: minimum id per root (out pre-filled with out[v] = v,
+// so a root needs no atomic), then a gather.
+template <bool R>
 __global__ void k_pool_labels_min(int32_t* __restrict__ arena, int32_t base, int32_t n, int32_t* __restrict__ out,
                                   int* __restrict__ flags) {
   for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
-    const int32_t r = find_halve(arena, base + v, n, flags);
+    const int32_t r = find_halve<R>(arena, base + v, n, flags);
     if (r == base + v) continue;
     if (ld(arena + base + v) != r) st(arena + base + v, r);
     if (ld(out + (r - base)) > v) atomicMin(out + (r - base), v);  // see k_labels_min
   }
 }
 
+template <bool R>
 __global__ void k_pool_labels_gather(const int32_t* __restrict__ arena, int32_t base, int32_t n,
                                      int32_t* __restrict__ out, int* __restrict__ flags) {
   for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
-    out[v] = out[find_read(arena, base + v, n, flags) - base];
+    out[v] = out[find_read<R>(arena, base + v, n, flags) - base];
 }
 
-// Image conversion for save / load: arena ids <-> graph-local ids.
+// Image conversion for save / load: arena ids <-> graph-local ids.  Done in
+// unsigned arithmetic: under union by rank a root's word carries its rank in
+// the top bits, and the id below them (local id + base < 2^kRankShift) never
+// carries into or borrows from them.
 __global__ void k_to_local(const int32_t* __restrict__ arena, int32_t base, int32_t n, int32_t* __restrict__ out) {
   for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
-    out[v] = arena[base + v] - base;
+    out[v] = (int32_t)((uint32_t)arena[base + v] - (uint32_t)base);
 }
 
 // Check a graph-local image before it is placed: every entry in range and
@@ -224,7 +235,7 @@ __global__ void k_check_image(const int32_t* __restrict__ img, int32_t n, unsign
 
 __global__ void k_place(const int32_t* __restrict__ img, int32_t base, int32_t n, int32_t* __restrict__ arena) {
   for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
-    arena[base + v] = img[v] + base;
+    arena[base + v] = (int32_t)((uint32_t)img[v] + (uint32_t)base);
 }
 
 }  // namespace

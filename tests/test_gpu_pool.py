@@ -31,7 +31,9 @@ def small_graphs(G, seed=5):
 
 @pytest.mark.parametrize("opts", [dict(), dict(hook=1), dict(items=1, block=64, grid_cap=5),
                                   dict(items=8, block=512, compress_linked=0, query_halving=0),
-                                  dict(one_launch=1), dict(one_launch=1, hook=1, items=1, grid_cap=3)],
+                                  dict(one_launch=1), dict(one_launch=1, hook=1, items=1, grid_cap=3),
+                                  dict(hook=2), dict(hook=2, compress_linked=0, items=8, block=1024),
+                                  dict(one_launch=1, hook=2, grid_cap=7)],
                          ids=lambda o: ",".join("%s=%s" % kv for kv in sorted(o.items())) or "default")
 def test_pool_steps_match_oracle(cc, opts):
     G = 96
@@ -142,3 +144,48 @@ def test_pool_gaps_eviction_and_images(cc):
     assert pool.sync() == cc.cc.CC_ERANGE
     assert pool.num_components(c) == 3000 - 2
     pool.close()
+
+
+def test_pool_rank_images_and_limits(cc):
+    """Union by rank in a pool: a graph's image carries ranks in its roots'
+    words; it round-trips through another slot and through a standalone
+    graph, a cyclic image is refused, and rank needs ids below 2^27."""
+    pool = cc.Pool(9000, 4, hook=2)
+    a = pool.add(3000)
+    b = pool.add(3000)
+    eb = synth.uniform_pairs(synth.key(13, 0, 1), 0, 4000, 3000)
+    pool.run([(a, cc.UPDATE, dev(eb[:2000]), None), (b, cc.UPDATE, dev(eb[2000:]), None)])
+    pool.run([(a, cc.UPDATE, dev(eb[2000:]), None)])
+    ref = oracle.UnionFind(3000)
+    ref.bulk_update(eb)
+    np.testing.assert_array_equal(pool.labels(a).cpu().numpy(), ref.labels())
+    img = pool.save(a)
+    words = np.frombuffer(bytes(img), np.int32, offset=16)
+    assert (words.view(np.uint32) >> 27).max() > 0, "no root carries a rank"
+    c = pool.add(3000)
+    pool.load(c, img)
+    np.testing.assert_array_equal(pool.labels(c).cpu().numpy(), ref.labels())
+    assert pool.num_components(c) == ref.num_components()
+    q = synth.uniform_pairs(synth.key(13, 0, 2), 0, 3000, 3000)
+    out = torch.empty(len(q), dtype=torch.uint8, device="cuda")
+    pool.run([(c, cc.QUERY, dev(q), out)])
+    np.testing.assert_array_equal(out.cpu().numpy(), ref.bulk_query(q))
+    g = cc.Graph(3000, hook=2)
+    g.load(img)
+    np.testing.assert_array_equal(g.labels().cpu().numpy(), ref.labels())
+    g.close()
+    bad = bytearray(img)
+    par = np.frombuffer(bad, np.int32, offset=16)
+    x = int(np.flatnonzero((par & ((1 << 27) - 1)) != np.arange(3000))[0])
+    par[x], par[int(par[x]) & ((1 << 27) - 1)] = int(par[x]) & ((1 << 27) - 1), x  # two-cycle
+    with pytest.raises(cc.CCError) as ei:
+        pool.load(c, bad)
+    assert ei.value.code == cc.cc.CC_ECORRUPT
+    np.testing.assert_array_equal(pool.labels(c).cpu().numpy(), ref.labels())
+    assert pool.sync() == cc.cc.CC_OK
+    pool.close()
+    big = cc.Pool((1 << 27) + 1, 2)
+    with pytest.raises(cc.CCError) as ei:
+        big.set_option("hook", 2)
+    assert ei.value.code == cc.cc.CC_EINVAL
+    big.close()
