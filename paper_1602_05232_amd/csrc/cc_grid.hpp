@@ -46,7 +46,12 @@ __device__ __forceinline__ bool grid_sync(unsigned* bar, unsigned& gen, int* fla
     int good = 1;
     const unsigned arrived = __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
     if (arrived == gridDim.x * target) {
-      __hip_atomic_store(bar + 32, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      // The last arrival passes the others' releases on: its acquire fence
+      // synchronizes with every block's release fence (their increments are
+      // in the release sequence it read), and its release store of the
+      // generation with every waiter's acquire fence below.
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      __hip_atomic_store(bar + 32, target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     } else {
       unsigned spins = 0;
       while (bar_load(bar + 32) < target) {
