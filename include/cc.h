@@ -59,7 +59,7 @@ enum cc_option {
   /* Bulk-Update schedule.  0 = fused: one kernel finds both roots and links
    * them with a compare-and-swap in place.  1 = split: a filter kernel
    * relabels edges by their roots and compacts the pairs with distinct roots
-   * (Algorithm 2, lines 1-2) into a live list, a link kernel joins the live
+   * (the relabel and filter of Algorithm 2) into a live list, a link kernel joins the live
    * root pairs, a compress kernel points the linked roots at their new root.
    * 2 = contracting: Algorithm 2 with its connected-components step done on
    * the contracted edge list A'' by rounds of hooking and shortcutting (one

@@ -2,7 +2,7 @@
 //
 //   k_init           parent[v] = v                       (initial state, Section 4)
 //   k_update_fused   Bulk-Update in one pass: both roots, then link in place
-//   k_filter         Algorithm 2 lines 1-2: relabel each edge by its roots and
+//   k_filter         Algorithm 2, relabel and filter: relabel each edge by its roots and
 //                    keep the pairs whose roots differ, compacted into a live
 //                    list (wavefront scan + LDS staging, one atomic per block)
 //   k_link_live      join every live root pair (stands in for Algorithm 2's
