@@ -1,0 +1,80 @@
+"""Seeded sweep over option combinations and workload shapes: every answer,
+label and count bit-exact against the oracle.  Each case prints its seed and
+options before it runs."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+SCHEDULES = [dict(update_mode=0), dict(update_mode=1), dict(update_mode=2), dict(find=1)]
+
+
+def case_options(rng):
+    o = dict(SCHEDULES[int(rng.integers(len(SCHEDULES)))])
+    hooks = [0, 1] if o.get("update_mode", 0) != 0 else [0, 1, 2]
+    o["hook"] = int(rng.choice(hooks))
+    o["block"] = int(rng.choice([64, 128, 256, 512, 1024]))
+    o["items"] = int(rng.choice([0, 1, 2, 4, 8]))
+    o["grid_cap"] = int(rng.choice([1, 2, 7, 64, 4096]))
+    o["query_halving"] = int(rng.integers(2))
+    o["compress_linked"] = int(rng.integers(2))
+    o["compress_every"] = int(rng.choice([0, 0, 1, 3]))
+    return o
+
+
+def case_stream(rng, seed):
+    kind = int(rng.integers(5))
+    if kind == 0:
+        n = int(rng.choice([1, 2, 17, 1000, 1 << 12]))
+        sizes = [int(x) for x in rng.integers(0, 3 * n + 2, size=int(rng.integers(1, 6)))]
+        e = synth.uniform_pairs(synth.key(seed, 0, 1), 0, sum(sizes), n)
+        q = synth.uniform_pairs(synth.key(seed, 0, 2), 0, 300 * len(sizes), n)
+        return synth.Stream("uniform", n, e, synth._offsets(sizes), q, synth._offsets([300] * len(sizes)))
+    if kind == 1:
+        return synth.rmat_stream(scale=int(rng.integers(8, 15)), size_lo=6, size_hi=13, qbatch=512,
+                                 seed=seed, probes=0)
+    if kind == 2:
+        W = int(rng.integers(2, 90))
+        return synth.grid_stream_cfg(W=W, H=int(rng.integers(1, 90)), batch=int(rng.choice([16, 500, 4096])),
+                                     qbatch=128, probes=0)
+    if kind == 3:
+        return synth.grid3d_stream_cfg(L=int(rng.integers(2, 20)), batch=int(rng.choice([64, 1000])), qbatch=128,
+                                       probes=0)
+    return synth.local_stream(n=int(rng.choice([100, 5000, 1 << 14])), degree=int(rng.choice([1, 5, 16])),
+                              window=int(rng.choice([1, 64, 1 << 10])), batch=int(rng.choice([64, 4096])),
+                              qbatch=256, probes=0)
+
+
+@pytest.fixture(scope="module")
+def cc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1602_05232_amd as ccgpu
+    ccgpu.lib()
+    return ccgpu
+
+
+@pytest.mark.parametrize("seed", range(200))
+def test_random_config(cc, seed):
+    rng = np.random.default_rng(1000 + seed)
+    opts = case_options(rng)
+    s = case_stream(rng, 7000 + seed)
+    print("case %d: %s n=%d edges=%d batches=%d opts=%s" % (seed, s.name, s.n, len(s.edges), s.num_batches, opts),
+          flush=True)
+    ref = oracle.UnionFind(s.n)
+    g = cc.Graph(s.n, **opts)
+    for i in range(s.num_batches):
+        b, q = s.batch(i), s.query(i)
+        ref.bulk_update(b)
+        g.bulk_update(torch.from_numpy(np.ascontiguousarray(b)).cuda())
+        if len(q):
+            got = g.bulk_query(torch.from_numpy(np.ascontiguousarray(q)).cuda()).cpu().numpy()
+            np.testing.assert_array_equal(got, ref.bulk_query(q), err_msg="answers after minibatch %d" % i)
+    np.testing.assert_array_equal(g.labels().cpu().numpy(), ref.labels())
+    assert g.num_components() == ref.num_components() == g.count_roots()
+    assert g.sync() == cc.cc.CC_OK
+    g.close()
