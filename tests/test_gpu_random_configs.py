@@ -78,3 +78,47 @@ def test_random_config(cc, seed):
     assert g.num_components() == ref.num_components() == g.count_roots()
     assert g.sync() == cc.cc.CC_OK
     g.close()
+
+
+def pool_options(rng):
+    return dict(hook=int(rng.integers(3)), block=int(rng.choice([64, 256, 1024])),
+                items=int(rng.choice([0, 1, 2, 4, 8])), grid_cap=int(rng.choice([1, 3, 64, 4096])),
+                query_halving=int(rng.integers(2)), compress_linked=int(rng.integers(2)),
+                one_launch=int(rng.integers(2)))
+
+
+@pytest.mark.parametrize("seed", range(60))
+def test_random_pool_config(cc, seed):
+    """Random graph mixes in one pool, several operations per graph in one
+    run (so runs have several rounds), against one oracle per graph."""
+    rng = np.random.default_rng(5000 + seed)
+    opts = pool_options(rng)
+    G = int(rng.integers(1, 40))
+    ns = [int(x) for x in rng.integers(1, 3000, size=G)]
+    print("pool case %d: G=%d sum_n=%d opts=%s" % (seed, G, sum(ns), opts), flush=True)
+    pool = cc.Pool(sum(ns) + int(rng.integers(0, 100)), G, **opts)
+    ids = [pool.add(n) for n in ns]
+    refs = [oracle.UnionFind(n) for n in ns]
+    for run in range(int(rng.integers(1, 4))):
+        ops, checks = [], []
+        for g in rng.permutation(G):
+            g = int(g)
+            for k in range(int(rng.integers(0, 4))):
+                if rng.random() < 0.6:
+                    e = synth.uniform_pairs(synth.key(9000 + seed, g, 10 * run + k), 0,
+                                            int(rng.integers(0, 4 * ns[g] + 2)), ns[g])
+                    refs[g].bulk_update(e)
+                    ops.append((ids[g], cc.UPDATE, torch.from_numpy(e).cuda(), None))
+                else:
+                    q = synth.uniform_pairs(synth.key(9100 + seed, g, 10 * run + k), 0, int(rng.integers(0, 500)), ns[g])
+                    out = torch.empty(len(q), dtype=torch.uint8, device="cuda")
+                    ops.append((ids[g], cc.QUERY, torch.from_numpy(q).cuda(), out))
+                    checks.append((out, refs[g].bulk_query(q), g))
+        pool.run(ops)
+        for out, want, g in checks:
+            np.testing.assert_array_equal(out.cpu().numpy(), want, err_msg="graph %d, run %d" % (g, run))
+    for g in range(G):
+        np.testing.assert_array_equal(pool.labels(ids[g]).cpu().numpy(), refs[g].labels(), err_msg="graph %d" % g)
+        assert pool.num_components(ids[g]) == refs[g].num_components()
+    assert pool.sync() == cc.cc.CC_OK
+    pool.close()
