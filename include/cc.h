@@ -158,7 +158,9 @@ int cc_bulk_query(cc_graph* g, const int32_t* pairs, int64_t q, uint8_t* out);
  * Section 1).  edges and pairs are device int32[][2]; eoff and qoff are
  * DEVICE int64[batches+1] item offsets into them; out is device uint8 indexed
  * like pairs.  max_items (>= 1) bounds the items of any one operation and
- * sizes the grid.  The operations are separated by device-wide barriers
+ * sizes the grid: ceil(max_items / CC_OPT_BLOCK) blocks of CC_OPT_BLOCK
+ * threads, at most CC_OPT_GRID_CAP, 1024 and what can be resident with one
+ * block per compute unit to spare.  The operations are separated by device-wide barriers
  * inside one cooperative launch, for streams of many small minibatches whose
  * separate launches would cost mostly launch latency.  Not available during
  * capture.  A barrier that waits past CC_OPT_SPIN_LIMIT ends the kernel and

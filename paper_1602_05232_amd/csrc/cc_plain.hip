@@ -732,13 +732,13 @@ namespace {
 template <class Ord>
 int launch_stream(cc_graph* g, int64_t batches, const int32_t* edges, const int64_t* eoff, const int32_t* pairs,
                   const int64_t* qoff, uint8_t* out, int64_t max_items) {
-  const int block = 256;
+  const int block = g->tune.block;
   int per_cu = 0, cus = 0;
   HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_stream<Ord>, block, 0));
   HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device));
   int64_t grid = (max_items + block - 1) / block;
   grid = std::min<int64_t>(grid, cc::coop_limit(per_cu, cus));
-  grid = std::min<int64_t>(grid, 1024);
+  grid = std::min<int64_t>(grid, std::min<int64_t>(1024, (int64_t)g->tune.grid_cap));
   grid = std::max<int64_t>(grid, 1);
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, g->stream, g->gbar, kBarWords);
   HIP_TRY(hipGetLastError());
