@@ -36,7 +36,9 @@ def run_stream(cc, s, opts, max_items=None):
 
 
 @pytest.mark.parametrize("which", ["grid", "er", "rmat"])
-@pytest.mark.parametrize("opts", [dict(), dict(hook=1), dict(hook=2)], ids=["id", "hash", "rank"])
+@pytest.mark.parametrize("opts", [dict(), dict(hook=1), dict(hook=2), dict(block=64, grid_cap=3),
+                                  dict(block=1024, grid_cap=1, hook=2), dict(block=128, hook=1)],
+                         ids=["id", "hash", "rank", "b64-g3", "b1024-g1-rank", "b128-hash"])
 def test_stream_kernel_matches_oracle(cc, which, opts):
     if which == "grid":
         s = synth.grid_stream_cfg(W=256, H=256, batch=1 << 12, qbatch=1 << 10)
