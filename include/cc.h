@@ -60,7 +60,8 @@ enum cc_option {
    * them with a compare-and-swap in place.  1 = split: a filter kernel
    * relabels edges by their roots and compacts the pairs with distinct roots
    * (the relabel and filter of Algorithm 2) into a live list, a link kernel joins the live
-   * root pairs, a compress kernel points the linked roots at their new root.
+   * root pairs, a compress kernel points the linked roots at their new root;
+   * at most 2^31 - 1 edges per call.
    * 2 = contracting: Algorithm 2 with its connected-components step done on
    * the contracted edge list A'' by rounds of hooking and shortcutting (one
    * cooperative launch; 8 bytes of scratch per edge of the largest

@@ -227,7 +227,7 @@ __global__ void k_bulk_find(int32_t* __restrict__ parent, const int2* __restrict
       for (long long t = chunk[1] + tid; t < K; t += B) sc.log[chunk[0] + t] = -1;
     const int wouts = wave_sum(outs);
     if ((tid & 63) == 0 && wouts > 0) atomicAdd(count_group(groups, level + 1) + slot, (unsigned)wouts);
-    if (level > n + 1) {  // deeper than any forest
+    if ((int64_t)level > (int64_t)n + 1) {  // deeper than any forest
       raise_flag(flags, kFlagCorrupt);
       break;
     }

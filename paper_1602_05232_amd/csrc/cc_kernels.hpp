@@ -198,13 +198,13 @@ __global__ void k_link_live(int32_t* __restrict__ parent, const int2* __restrict
 template <bool R = false>
 __device__ __forceinline__ void compress_path(int32_t* parent, int32_t x, int32_t n, int* flags) {
   const int32_t r = find_read<R>(parent, x, n, flags);
-  int32_t steps = 0;
+  uint32_t steps = 0;
   int32_t p = ldp<R>(parent + x);
   while (p != r && p != x) {
     st(parent + x, r);
     x = p;
     p = ldp<R>(parent + x);
-    if (++steps > n) break;
+    if (++steps > (uint32_t)n) break;
   }
 }
 

@@ -481,6 +481,10 @@ extern "C" int cc_bulk_update(cc_graph* g, const int32_t* edges, int64_t m) {
     int rc = hashed ? launch_contract_t<ByHash>(g, e, m) : launch_contract_t<ById>(g, e, m);
     if (rc != CC_OK) return rc;
   } else if (g->tune.mode == 1) {
+    if (m > 0x7fffffffLL) {  // the live count is a 32-bit device counter
+      cc_set_error("cc_bulk_update: the split update takes at most 2^31-1 edges per call");
+      return CC_EINVAL;
+    }
     if (g->capturing && m > g->live_cap) {
       cc_set_error("cc_bulk_update: split update of %lld edges exceeds the reserved %lld during capture",
                    (long long)m, (long long)g->live_cap);

@@ -166,14 +166,17 @@ __global__ void k_pool_rounds(const OpDesc* __restrict__ ops, const int32_t* __r
 }
 
 __global__ void k_init_range(int32_t* __restrict__ arena, int32_t base, int32_t n) {
-  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = (int32_t)i;
     arena[base + v] = base + v;
+  }
 }
 
 // Labels of one pool graph, graph-local: id order (root = minimum).
 __global__ void k_pool_labels_id(int32_t* __restrict__ arena, int32_t base, int32_t n, int32_t* __restrict__ out,
                                  int* __restrict__ flags) {
-  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = (int32_t)i;
     const int32_t r = find_halve(arena, base + v, n, flags);
     if (ld(arena + base + v) != r) st(arena + base + v, r);
     out[v] = r - base;
@@ -185,7 +188,8 @@ __global__ void k_pool_labels_id(int32_t* __restrict__ arena, int32_t base, int3
 template <bool R>
 __global__ void k_pool_labels_min(int32_t* __restrict__ arena, int32_t base, int32_t n, int32_t* __restrict__ out,
                                   int* __restrict__ flags) {
-  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = (int32_t)i;
     const int32_t r = find_halve<R>(arena, base + v, n, flags);
     if (r == base + v) continue;
     if (ld(arena + base + v) != r) st(arena + base + v, r);
@@ -196,8 +200,10 @@ __global__ void k_pool_labels_min(int32_t* __restrict__ arena, int32_t base, int
 template <bool R>
 __global__ void k_pool_labels_gather(const int32_t* __restrict__ arena, int32_t base, int32_t n,
                                      int32_t* __restrict__ out, int* __restrict__ flags) {
-  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = (int32_t)i;
     out[v] = out[find_read<R>(arena, base + v, n, flags) - base];
+  }
 }
 
 // Image conversion for save / load: arena ids <-> graph-local ids.  Done in
@@ -205,8 +211,10 @@ __global__ void k_pool_labels_gather(const int32_t* __restrict__ arena, int32_t 
 // the top bits, and the id below them (local id + base < 2^kRankShift) never
 // carries into or borrows from them.
 __global__ void k_to_local(const int32_t* __restrict__ arena, int32_t base, int32_t n, int32_t* __restrict__ out) {
-  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = (int32_t)i;
     out[v] = (int32_t)((uint32_t)arena[base + v] - (uint32_t)base);
+  }
 }
 
 // Check a graph-local image before it is placed: every entry in range and
@@ -215,7 +223,8 @@ __global__ void k_to_local(const int32_t* __restrict__ arena, int32_t base, int3
 template <bool HASH>
 __global__ void k_check_image(const int32_t* __restrict__ img, int32_t n, unsigned long long* __restrict__ res) {
   unsigned long long bad = 0, roots = 0;
-  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = (int32_t)i;
     const int32_t q = img[v];
     if (q < 0 || q >= n) {
       ++bad;
@@ -234,8 +243,10 @@ __global__ void k_check_image(const int32_t* __restrict__ img, int32_t n, unsign
 }
 
 __global__ void k_place(const int32_t* __restrict__ img, int32_t base, int32_t n, int32_t* __restrict__ arena) {
-  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = (int32_t)i;
     arena[base + v] = (int32_t)((uint32_t)img[v] + (uint32_t)base);
+  }
 }
 
 }  // namespace

@@ -10,7 +10,8 @@ namespace {  // kernels get internal linkage in every translation unit
 // Each vertex is also pointed straight at its root.
 __global__ void k_labels_id(int32_t* __restrict__ parent, int32_t n, int32_t* __restrict__ out,
                             int* __restrict__ flags) {
-  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = (int32_t)i;
     const int32_t r = find_halve(parent, v, n, flags);
     if (ld(parent + v) != r) st(parent + v, r);
     out[v] = r;
@@ -18,11 +19,17 @@ __global__ void k_labels_id(int32_t* __restrict__ parent, int32_t n, int32_t* __
 }
 
 __global__ void k_fill_i32(int32_t* __restrict__ out, int32_t n, int32_t value) {
-  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) out[v] = value;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = (int32_t)i;
+    out[v] = value;
+  }
 }
 
 __global__ void k_iota_i32(int32_t* __restrict__ out, int32_t n) {
-  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) out[v] = v;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = (int32_t)i;
+    out[v] = v;
+  }
 }
 
 // Hashed or rank order, pass 1: the minimum id of each tree collects in its
@@ -31,7 +38,8 @@ __global__ void k_iota_i32(int32_t* __restrict__ out, int32_t n) {
 template <bool R = false>
 __global__ void k_labels_min(int32_t* __restrict__ parent, int32_t n, int32_t* __restrict__ out,
                              int* __restrict__ flags) {
-  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = (int32_t)i;
     const int32_t r = find_halve<R>(parent, v, n, flags);
     if (r == v) continue;
     if (ld(parent + v) != r) st(parent + v, r);
@@ -47,7 +55,8 @@ __global__ void k_labels_min(int32_t* __restrict__ parent, int32_t n, int32_t* _
 template <bool R = false>
 __global__ void k_labels_gather(const int32_t* __restrict__ parent, int32_t n, int32_t* __restrict__ out,
                                 int* __restrict__ flags) {
-  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = (int32_t)i;
     const int32_t r = find_read<R>(parent, v, n, flags);
     out[v] = out[r];
   }
@@ -55,7 +64,8 @@ __global__ void k_labels_gather(const int32_t* __restrict__ parent, int32_t n, i
 
 template <bool R = false>
 __global__ void k_compress_all(int32_t* __restrict__ parent, int32_t n, int* __restrict__ flags) {
-  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = (int32_t)i;
     const int32_t r = find_halve<R>(parent, v, n, flags);
     if (r != v && ld(parent + v) != r) st(parent + v, r);
   }
@@ -66,8 +76,10 @@ __global__ void k_count_roots(const int32_t* __restrict__ parent, int32_t n,
                               unsigned long long* __restrict__ result) {
   __shared__ int part[16];
   int c = 0;
-  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = (int32_t)i;
     c += pid<R>(parent[v]) == v;
+  }
   c = wave_sum(c);
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
   __syncthreads();

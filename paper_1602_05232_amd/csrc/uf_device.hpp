@@ -21,8 +21,9 @@
 //    other than itself never becomes a root again) and writes one of its
 //    ancestors, so it can never undo a link or create a cycle, whatever order
 //    the stores land in.
-//  * Every walk counts its steps; more than n steps means the array holds a
-//    cycle, which is latched as "corrupt" and ends the walk.
+//  * Every walk counts its steps (unsigned, so the count cannot overflow
+//    before it passes n, even at n = 2^31 - 1); more than n steps means the
+//    array holds a cycle, which is latched as "corrupt" and ends the walk.
 //
 // Kernel boundaries give each bulk operation a consistent view of the
 // previous one (stream order), which realises the rule that a bulk operation
@@ -99,14 +100,14 @@ __device__ __forceinline__ int32_t ldp(const int32_t* p) {
 template <bool R = false>
 __device__ __forceinline__ int32_t find_halve_from(int32_t* parent, int32_t x, int32_t p, int32_t cap,
                                                    int* flags) {
-  int32_t steps = 0;
+  uint32_t steps = 0;
   while (p != x) {
     int32_t g = ldp<R>(parent + p);
     if (g == p) return p;
     st(parent + x, g);
     x = g;
     p = ldp<R>(parent + x);
-    if (++steps > cap) {
+    if (++steps > (uint32_t)cap) {
       raise_flag(flags, kFlagCorrupt);
       return x;
     }
@@ -124,11 +125,11 @@ __device__ __forceinline__ int32_t find_halve(int32_t* parent, int32_t x, int32_
 template <bool R = false>
 __device__ __forceinline__ int32_t find_read(const int32_t* parent, int32_t x, int32_t cap, int* flags) {
   int32_t p = ldp<R>(parent + x);
-  int32_t steps = 0;
+  uint32_t steps = 0;
   while (p != x) {
     x = p;
     p = ldp<R>(parent + x);
-    if (++steps > cap) {
+    if (++steps > (uint32_t)cap) {
       raise_flag(flags, kFlagCorrupt);
       return x;
     }
@@ -148,7 +149,7 @@ __device__ __forceinline__ int32_t find_root(int32_t* parent, int32_t x, int32_t
 template <class Ord>
 __device__ __forceinline__ int32_t link_roots(int32_t* parent, int32_t a, int32_t b, int32_t cap,
                                               int* flags, const Ord& ord) {
-  int32_t steps = 0;
+  uint32_t steps = 0;
   while (a != b) {
     const bool a_wins = ord.above(a, b);
     const int32_t hi = a_wins ? b : a;  // loses: gets linked under the other
@@ -158,7 +159,7 @@ __device__ __forceinline__ int32_t link_roots(int32_t* parent, int32_t a, int32_
     // hi stopped being a root; continue from its current parent
     const int32_t r = find_halve(parent, old, cap, flags);
     if (a_wins) b = r; else a = r;
-    if (++steps > cap) {
+    if (++steps > (uint32_t)cap) {
       raise_flag(flags, kFlagCorrupt);
       return -1;
     }
@@ -174,7 +175,7 @@ __device__ __forceinline__ int32_t link_roots(int32_t* parent, int32_t a, int32_
 // A rank increment that loses a race is skipped; ranks only steer balance.
 __device__ __forceinline__ int32_t link_roots_rank(int32_t* parent, int32_t a, int32_t b, int32_t cap,
                                                    int* flags) {
-  int32_t steps = 0;
+  uint32_t steps = 0;
   while (a != b) {
     const int32_t wa = ld(parent + a), wb = ld(parent + b);
     if ((wa & kIdMask) != a) {
@@ -191,7 +192,7 @@ __device__ __forceinline__ int32_t link_roots_rank(int32_t* parent, int32_t a, i
         return lo;
       }
     }
-    if (++steps > cap) {
+    if (++steps > (uint32_t)cap) {
       raise_flag(flags, kFlagCorrupt);
       return -1;
     }
