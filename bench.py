@@ -409,9 +409,11 @@ def run_batched(args):
         ops += [(ids[g], ccgpu.QUERY, qslice(g, k, Qall), qslice(g, k, out)) for g in range(G)]
         ops_per_step.append(ops)
 
+    prepared = [pool.prepare(ops) for ops in ops_per_step]  # marshalled once, submitted every step
+
     def pool_step():
         pool.reset_all()
-        for ops in ops_per_step:
+        for ops in prepared:
             pool.run(ops)
         return pool.sync()
 
@@ -427,14 +429,18 @@ def run_batched(args):
             for k, v in {**dict(hook=0, compress_linked=1, block=256), **o}.items():
                 gr.set_option(k, v)
 
+    # views made once, as the pool's operation lists are marshalled once
+    pe = [[eslice(g, k) for g in range(G)] for k in range(4)]
+    pq = [[(qslice(g, k, Qall), qslice(g, k, out_plain)) for g in range(G)] for k in range(4)]
+
     def plain_step():
         for gr in graphs:
             gr.reset()
         for k in range(4):
             for g in range(G):
-                graphs[g].bulk_update(eslice(g, k))
+                graphs[g].bulk_update(pe[k][g])
             for g in range(G):
-                graphs[g].bulk_query(qslice(g, k, Qall), out=qslice(g, k, out_plain))
+                graphs[g].bulk_query(pq[k][g][0], out=pq[k][g][1])
         torch.cuda.synchronize()
 
     def timed(fn, name):
@@ -462,7 +468,7 @@ def run_batched(args):
     wall_pool = timed(pool_step, "pool")
     assert torch.equal(out, out_plain), "pool answers differ from per-graph answers"
     # the same run with all rounds of a step in one cooperative launch
-    ops_all = [op for ops in ops_per_step for op in ops]
+    ops_all = pool.prepare([op for ops in ops_per_step for op in ops])
     pool.set_option("one_launch", 1)
 
     def pool_one_launch():

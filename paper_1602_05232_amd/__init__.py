@@ -3,4 +3,4 @@
 Hot path: Bulk-Update and Bulk-Query over a union-find parent array in HBM,
 as hand-written HIP kernels behind the C ABI of include/cc.h (libcc.so).
 """
-from .cc import QUERY, UPDATE, CCError, Graph, Pool, lib  # noqa: F401
+from .cc import QUERY, UPDATE, CCError, Graph, Pool, PreparedOps, lib  # noqa: F401

@@ -314,6 +314,30 @@ class _Capture:
         return False
 
 
+class PreparedOps:
+    """An operation list for Pool.run as the cc_op array of cc_pool_run.  It
+    keeps the item and output tensors alive; their contents may change
+    between runs, their storage must not."""
+
+    def __init__(self, ops):
+        ops = list(ops)
+        arr = (CcOp * max(1, len(ops)))()
+        keep = []
+        for i, (gid, kind, items, out) in enumerate(ops):
+            cnt = items.shape[0] if items is not None and items.numel() else 0
+            arr[i].graph = int(gid)
+            arr[i].kind = int(kind)
+            arr[i].count = cnt
+            arr[i].items = _pairs_ptr(items, "items") if cnt else None
+            if kind == QUERY and cnt:
+                assert out is not None and out.dtype == torch.uint8 and out.is_cuda and out.numel() >= cnt
+                arr[i].out = out.data_ptr()
+            else:
+                arr[i].out = None
+            keep.append((items, out))
+        self.array, self.count, self._keep = arr, len(ops), keep
+
+
 class Pool:
     """Many independent graphs in one device arena (include/cc_pool.h).
 
@@ -396,20 +420,16 @@ class Pool:
                 merged.append((b, ln))
         return [ln for _, ln in merged]
 
+    @staticmethod
+    def prepare(ops) -> "PreparedOps":
+        """Marshal an operation list once, for runs that repeat it."""
+        return PreparedOps(ops)
+
     def run(self, ops):
-        arr = (CcOp * max(1, len(ops)))()
-        for i, (gid, kind, items, out) in enumerate(ops):
-            cnt = items.shape[0] if items is not None and items.numel() else 0
-            arr[i].graph = int(gid)
-            arr[i].kind = int(kind)
-            arr[i].count = cnt
-            arr[i].items = _pairs_ptr(items, "items") if cnt else None
-            if kind == QUERY and cnt:
-                assert out is not None and out.dtype == torch.uint8 and out.is_cuda and out.numel() >= cnt
-                arr[i].out = out.data_ptr()
-            else:
-                arr[i].out = None
-        _check(lib().cc_pool_run(self._h, arr, len(ops)))
+        """One cc_pool_run over ops: a list of (graph, kind, items, out) or a
+        PreparedOps."""
+        p = ops if isinstance(ops, PreparedOps) else PreparedOps(ops)
+        _check(lib().cc_pool_run(self._h, p.array, p.count))
 
     def labels(self, gid: int, out: torch.Tensor | None = None) -> torch.Tensor:
         n = self.vertices(gid)
