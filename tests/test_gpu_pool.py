@@ -189,3 +189,32 @@ def test_pool_rank_images_and_limits(cc):
         big.set_option("hook", 2)
     assert ei.value.code == cc.cc.CC_EINVAL
     big.close()
+
+
+def test_prepared_ops_rerun_with_new_contents(cc):
+    """A prepared operation list is submitted twice; between the runs the
+    pool is reset and the item tensors get new contents in place."""
+    G, n, m, q = 6, 500, 700, 300
+    pool = cc.Pool(G * n, G, hook=2)
+    ids = [pool.add(n) for _ in range(G)]
+    E = [torch.empty((m, 2), dtype=torch.int32, device="cuda") for _ in range(G)]
+    Q = [torch.empty((q, 2), dtype=torch.int32, device="cuda") for _ in range(G)]
+    O = [torch.empty(q, dtype=torch.uint8, device="cuda") for _ in range(G)]
+    prep = pool.prepare([(ids[g], cc.UPDATE, E[g], None) for g in range(G)] +
+                        [(ids[g], cc.QUERY, Q[g], O[g]) for g in range(G)])
+    for run in range(2):
+        pool.reset_all()
+        refs = []
+        for g in range(G):
+            e = synth.uniform_pairs(synth.key(41, g, 2 * run), 0, m, n)
+            qq = synth.uniform_pairs(synth.key(41, g, 2 * run + 1), 0, q, n)
+            E[g].copy_(torch.from_numpy(e))
+            Q[g].copy_(torch.from_numpy(qq))
+            ref = oracle.UnionFind(n)
+            ref.bulk_update(e)
+            refs.append(ref.bulk_query(qq))
+        pool.run(prep)
+        for g in range(G):
+            np.testing.assert_array_equal(O[g].cpu().numpy(), refs[g], err_msg="run %d graph %d" % (run, g))
+    assert pool.sync() == cc.cc.CC_OK
+    pool.close()
