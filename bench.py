@@ -541,8 +541,6 @@ def run_serve(args):
     popts = tuning.lookup("pool", "mixed", n) or {}
     popts = {k: v for k, v in popts.items() if k not in ("update_mode", "compress_every")}
     popts["compress_linked"] = 0  # rounds overlap on two streams
-    if popts.get("hook") == 2 and S * n > (1 << 27):
-        popts["hook"] = 1  # rank bits need arena ids below 2^27; 64 resident graphs exceed that
 
     def with_arrivals(times):
         out = []

@@ -54,8 +54,8 @@ int cc_pool_destroy(cc_pool* p);  /* waits for the stream */
 int cc_pool_set_stream(cc_pool* p, void* stream);
 /* Options of enum cc_option that apply to the pool: CC_OPT_BLOCK,
  * CC_OPT_ITEMS, CC_OPT_QUERY_HALVING, CC_OPT_HOOK 0, 1 or 2 (set before
- * adding graphs, CC_EINVAL once a graph exists; 2, union by rank, needs a
- * capacity of at most 2^27 vertices), CC_OPT_GRID_CAP,
+ * adding graphs, CC_EINVAL once a graph exists; under 2, union by rank,
+ * cc_pool_add refuses graphs of more than 2^27 vertices), CC_OPT_GRID_CAP,
  * CC_OPT_COMPRESS_LINKED, CC_OPT_SPIN_LIMIT, CC_OPT_ONE_LAUNCH. */
 int cc_pool_set_option(cc_pool* p, int key, int64_t value);
 

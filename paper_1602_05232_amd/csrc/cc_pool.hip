@@ -33,7 +33,7 @@ struct RingSlot {
   OpDesc* host = nullptr;  // pinned staging
   OpDesc* dev = nullptr;
   int64_t cap = 0;
-  int32_t* hooked = nullptr;  // capacity entries, allocated on first use
+  int2* hooked = nullptr;     // capacity entries (graph base, local id), allocated on first use
   unsigned* ctl = nullptr;    // [0] hooked count, [1] finished blocks
   int32_t* meta_host = nullptr;  // one-launch form: round starts, then round tiles
   int32_t* meta_dev = nullptr;
@@ -58,6 +58,8 @@ struct cc_pool {
   int64_t staging_cap = 0;
   unsigned long long* check = nullptr;  // [0] bad entries, [1] roots (image check)
   unsigned* bar = nullptr;              // device-wide barrier of the one-launch form
+  int2* table = nullptr;                // (base, n) of the graphs in use, for cc_pool_reset_all
+  std::vector<int2> table_host;
   RingSlot ring[kRing];
   int ring_next = 0;
   cc::Tuning tune;
@@ -119,7 +121,7 @@ int reserve_slot(cc_pool* p, int64_t count, bool record, RingSlot** out) {
     s->cap = cap;
   }
   if (record && !s->hooked) {
-    if (hipMalloc((void**)&s->hooked, (size_t)p->capacity * 4) != hipSuccess ||
+    if (hipMalloc((void**)&s->hooked, (size_t)p->capacity * sizeof(int2)) != hipSuccess ||
         hipMalloc((void**)&s->ctl, 64) != hipSuccess) {
       cc_set_error("cc_pool_run: hooked-list allocation failed");
       return CC_ENOMEM;
@@ -250,6 +252,8 @@ extern "C" cc_pool* cc_pool_create(int64_t capacity, int32_t max_graphs) {
     (void)hipFree(p->arena);
     (void)hipFree(p->glinks);
     (void)hipFree(p->flags);
+    (void)hipFree(p->bar);
+    (void)hipFree(p->table);
     delete p;
     return nullptr;
   };
@@ -258,6 +262,7 @@ extern "C" cc_pool* cc_pool_create(int64_t capacity, int32_t max_graphs) {
   if (hipMalloc(&p->glinks, (size_t)max_graphs * kPoolLinkStride * 8) != hipSuccess) return fail("links");
   if (hipMalloc(&p->flags, 64) != hipSuccess) return fail("flags");
   if (hipMalloc(&p->bar, kBarWords * sizeof(unsigned)) != hipSuccess) return fail("bar");
+  if (hipMalloc(&p->table, (size_t)max_graphs * sizeof(int2)) != hipSuccess) return fail("table");
   if (hipMemsetAsync(p->flags, 0, 64, p->stream) != hipSuccess) return fail("memset");
   if (hipMemsetAsync(p->glinks, 0, (size_t)max_graphs * kPoolLinkStride * 8, p->stream) != hipSuccess)
     return fail("memset");
@@ -287,6 +292,7 @@ extern "C" int cc_pool_destroy(cc_pool* p) {
   (void)hipFree(p->staging);
   (void)hipFree(p->check);
   (void)hipFree(p->bar);
+  (void)hipFree(p->table);
   delete p;
   return CC_OK;
 }
@@ -301,10 +307,6 @@ extern "C" int cc_pool_set_option(cc_pool* p, int key, int64_t value) {
   if (!p) return CC_EINVAL;
   if (key == CC_OPT_UPDATE_MODE || key == CC_OPT_COMPRESS_EVERY || key == CC_OPT_FIND) {
     cc_set_error("cc_pool_set_option: option %d does not apply to pools", key);
-    return CC_EINVAL;
-  }
-  if (key == CC_OPT_HOOK && value == 2 && p->capacity > (int64_t)kIdMask + 1) {
-    cc_set_error("cc_pool_set_option: union by rank needs a capacity of at most 2^%d vertices", kRankShift);
     return CC_EINVAL;
   }
   if (key == CC_OPT_HOOK) {
@@ -323,6 +325,10 @@ extern "C" int cc_pool_set_option(cc_pool* p, int key, int64_t value) {
 
 extern "C" int cc_pool_add(cc_pool* p, int64_t n, int32_t* id) {
   if (!p || !id || n < 1) return CC_EINVAL;
+  if (p->tune.hook == 2 && n > (int64_t)kIdMask + 1) {
+    cc_set_error("cc_pool_add: union by rank needs graphs of at most 2^%d vertices", kRankShift);
+    return CC_EINVAL;
+  }
   DeviceGuard dg(p->device);
   int32_t slot = -1;
   for (int32_t i = 0; i < p->max_graphs; ++i)
@@ -373,8 +379,18 @@ extern "C" int cc_pool_reset(cc_pool* p, int32_t id) {
 extern "C" int cc_pool_reset_all(cc_pool* p) {
   if (!p) return CC_EINVAL;
   DeviceGuard dg(p->device);
-  hipLaunchKernelGGL(k_init, dim3(blocks_for((p->capacity + 3) / 4, 256, 4096)), dim3(256), 0, p->stream, p->arena,
-                     p->capacity);
+  std::vector<int2>& t = p->table_host;
+  t.clear();
+  for (const auto& g : p->graphs)
+    if (g.used) t.push_back(make_int2((int32_t)g.base, (int32_t)g.n));
+  std::sort(t.begin(), t.end(), [](const int2& a, const int2& b) { return a.x < b.x; });
+  if (!t.empty()) {
+    // the host table is reused by the next call only after this copy has run
+    HIP_TRY(hipMemcpyAsync(p->table, t.data(), t.size() * sizeof(int2), hipMemcpyHostToDevice, p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    hipLaunchKernelGGL(k_pool_init_all, dim3(blocks_for(p->capacity, 256, 4096)), dim3(256), 0, p->stream, p->arena,
+                       p->capacity, p->table, (int)t.size());
+  }
   hipLaunchKernelGGL(k_zero_u64, dim3(64), dim3(256), 0, p->stream, p->glinks, p->max_graphs * kPoolLinkStride);
   HIP_TRY(hipGetLastError());
   return CC_OK;
@@ -515,11 +531,11 @@ extern "C" int cc_pool_run(cc_pool* p, const cc_op* ops, int32_t num_ops) {
     if (record) {
       const int32_t cap = (int32_t)std::min<int64_t>(p->capacity, 0x7fffffff);
       if (p->tune.hook == 2)
-        hipLaunchKernelGGL(k_compress_hooked<true>, dim3(1024), dim3(256), 0, p->stream, p->arena, slot->hooked,
-                           slot->ctl, cap, p->flags);
+        hipLaunchKernelGGL(k_pool_compress_hooked<true>, dim3(1024), dim3(256), 0, p->stream, p->arena,
+                           slot->hooked, slot->ctl, cap, p->flags);
       else
-        hipLaunchKernelGGL(k_compress_hooked<false>, dim3(1024), dim3(256), 0, p->stream, p->arena, slot->hooked,
-                           slot->ctl, cap, p->flags);
+        hipLaunchKernelGGL(k_pool_compress_hooked<false>, dim3(1024), dim3(256), 0, p->stream, p->arena,
+                           slot->hooked, slot->ctl, cap, p->flags);
     }
   }
   HIP_TRY(hipGetLastError());
@@ -621,17 +637,14 @@ extern "C" int cc_pool_save(cc_pool* p, int32_t id, void* host_buf) {
   if (!valid_graph(p, id) || !host_buf) return CC_EINVAL;
   DeviceGuard dg(p->device);
   const PoolGraph& g = p->graphs[(size_t)id];
-  int rc = ensure_staging(p, g.n);
-  if (rc != CC_OK) return rc;
   unsigned long long links = 0;
-  rc = read_graph_links(p, id, &links);
+  int rc = read_graph_links(p, id, &links);
   if (rc != CC_OK) return rc;
   int64_t hdr[2] = {g.n, (int64_t)links};
   memcpy(host_buf, hdr, 16);
-  hipLaunchKernelGGL(k_to_local, dim3(blocks_for(g.n, 256, 4096)), dim3(256), 0, p->stream, p->arena,
-                     (int32_t)g.base, (int32_t)g.n, p->staging);
-  HIP_TRY(hipGetLastError());
-  HIP_TRY(hipMemcpyAsync((char*)host_buf + 16, p->staging, (size_t)g.n * 4, hipMemcpyDeviceToHost, p->stream));
+  // the graph's slots hold graph-local ids: they are the image as they are
+  HIP_TRY(hipMemcpyAsync((char*)host_buf + 16, p->arena + g.base, (size_t)g.n * 4, hipMemcpyDeviceToHost,
+                         p->stream));
   HIP_TRY(hipStreamSynchronize(p->stream));
   return CC_OK;
 }
@@ -646,41 +659,40 @@ extern "C" int cc_pool_load(cc_pool* p, int32_t id, const void* host_buf) {
     cc_set_error("cc_pool_load: image has n=%lld, graph has n=%lld", (long long)hdr[0], (long long)g.n);
     return CC_EINVAL;
   }
-  if (p->tune.hook == 2) {
-    // a rank image keeps ranks, not the order, in its words: walk it on the host
-    int64_t roots = 0;
-    if (!cc::check_forest(reinterpret_cast<const int32_t*>((const char*)host_buf + 16), g.n, 2, &roots) ||
-        hdr[1] != g.n - roots) {
-      cc_set_error("cc_pool_load: image is not a forest");
-      return CC_ECORRUPT;
-    }
-  }
-  int rc = ensure_staging(p, g.n);
+  int rc = ensure_staging(p, p->tune.hook == 2 ? 2 * g.n : g.n);
   if (rc != CC_OK) return rc;
   const unsigned blocks = blocks_for(g.n, 256, 4096);
   HIP_TRY(hipMemcpyAsync(p->staging, (const char*)host_buf + 16, (size_t)g.n * 4, hipMemcpyHostToDevice,
                          p->stream));
-  if (p->tune.hook != 2) {
-    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, p->stream, p->check, 2);
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, p->stream, p->check, 2);
+  if (p->tune.hook == 2) {
+    // a rank image keeps ranks, not an order, in its words: every vertex must
+    // reach a root by pointer doubling (scratch: the second half of staging)
+    int32_t* r = p->staging + g.n;
+    hipLaunchKernelGGL(k_rank_image_init, dim3(blocks), dim3(256), 0, p->stream, p->staging, (int32_t)g.n, r,
+                       p->check);
+    for (int k = 0; k < 32; ++k)
+      hipLaunchKernelGGL(k_rank_image_jump, dim3(blocks), dim3(256), 0, p->stream, r, (int32_t)g.n);
+    hipLaunchKernelGGL(k_rank_image_verify, dim3(blocks), dim3(256), 0, p->stream, p->staging, r, (int32_t)g.n,
+                       p->check);
+  } else {
     if (p->tune.hook == 1)
       hipLaunchKernelGGL(k_check_image<true>, dim3(blocks), dim3(256), 0, p->stream, p->staging, (int32_t)g.n,
                          p->check);
     else
       hipLaunchKernelGGL(k_check_image<false>, dim3(blocks), dim3(256), 0, p->stream, p->staging, (int32_t)g.n,
                          p->check);
-    HIP_TRY(hipGetLastError());
-    unsigned long long res[2] = {0, 0};
-    HIP_TRY(hipMemcpyAsync(res, p->check, 16, hipMemcpyDeviceToHost, p->stream));
-    HIP_TRY(hipStreamSynchronize(p->stream));
-    if (res[0] != 0 || hdr[1] != g.n - (int64_t)res[1]) {
-      cc_set_error("cc_pool_load: image is not a forest under the pool's linking order");
-      return CC_ECORRUPT;
-    }
+  }
+  HIP_TRY(hipGetLastError());
+  unsigned long long res[2] = {0, 0};
+  HIP_TRY(hipMemcpyAsync(res, p->check, 16, hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  if (res[0] != 0 || hdr[1] != g.n - (int64_t)res[1]) {
+    cc_set_error("cc_pool_load: image is not a forest under the pool's linking order");
+    return CC_ECORRUPT;
   }
   unsigned long long links = (unsigned long long)hdr[1];
-  hipLaunchKernelGGL(k_place, dim3(blocks), dim3(256), 0, p->stream, p->staging, (int32_t)g.base, (int32_t)g.n,
-                     p->arena);
-  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(p->arena + g.base, p->staging, (size_t)g.n * 4, hipMemcpyDeviceToDevice, p->stream));
   HIP_TRY(hipMemcpyAsync(p->glinks + (size_t)id * kPoolLinkStride, &links, 8, hipMemcpyHostToDevice, p->stream));
   HIP_TRY(hipStreamSynchronize(p->stream));
   return CC_OK;

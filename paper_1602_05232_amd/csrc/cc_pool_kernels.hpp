@@ -1,6 +1,7 @@
 // Kernels of the many-graph form: independent graphs share one parent arena
-// (graph g owns ids [base_g, base_g + n_g) and its parent entries hold arena
-// ids), and one launch runs one operation per graph for many graphs at once.
+// (graph g owns the slots [base_g, base_g + n_g), and those slots hold
+// graph-local ids, so arena + base_g is graph g's own parent array), and one
+// launch runs one operation per graph for many graphs at once.
 //
 // A launch is a list of op descriptors; op i covers tiles [tile0_i,
 // tile0_i + ntiles_i) of the launch's tile space, a tile being blockDim.x *
@@ -52,15 +53,17 @@ __device__ __forceinline__ int block_sum(int v, int* red) {
 }
 
 // One tile of one operation (block-uniform: every thread of the block calls it).
-// HOOK: 0 id order, 1 hashed priority (of graph-local ids), 2 union by rank
-// (arena ids keep each graph's local order, so ties break as in a lone graph;
-// the rank bits need arena ids below 2^kRankShift).
+// HOOK: 0 id order, 1 hashed priority, 2 union by rank; all on graph-local
+// ids, exactly as for a lone graph (rank needs n_g below 2^kRankShift).
+// With RECORD, each root this tile links is appended to `hooked` as (graph
+// base, local id).
 template <int ITEMS, int HOOK, bool RECORD, bool HALVE_Q>
 __device__ __forceinline__ void pool_tile(const OpDesc& op, uint32_t t, int32_t* __restrict__ arena,
                                           unsigned long long* __restrict__ glinks, int* __restrict__ flags,
-                                          int32_t* __restrict__ hooked, unsigned* __restrict__ hooked_ctl,
+                                          int2* __restrict__ hooked, unsigned* __restrict__ hooked_ctl,
                                           int* wave_off, unsigned* blk, int* red) {
   constexpr bool R = HOOK == 2;
+  int32_t* parent = arena + op.base;
   const uint32_t T = blockDim.x * ITEMS;
   const int64_t t0 = (int64_t)(t - op.tile0) * T;
   int2 e[ITEMS];
@@ -80,21 +83,15 @@ __device__ __forceinline__ void pool_tile(const OpDesc& op, uint32_t t, int32_t*
         continue;
       }
       if (e[k].x == e[k].y) continue;
-      const int32_t u = op.base + e[k].x, v = op.base + e[k].y;
-      const int32_t pu = ldp<R>(arena + u), pv = ldp<R>(arena + v);
+      const int32_t u = e[k].x, v = e[k].y;
+      const int32_t pu = ldp<R>(parent + u), pv = ldp<R>(parent + v);
       if (pu == pv || pu == v || pv == u) continue;
-      const int32_t ru = find_halve_from<R>(arena, u, pu, op.n, flags);
-      const int32_t rv = find_halve_from<R>(arena, v, pv, op.n, flags);
+      const int32_t ru = find_halve_from<R>(parent, u, pu, op.n, flags);
+      const int32_t rv = find_halve_from<R>(parent, v, pv, op.n, flags);
       if (ru != rv) {
-        if (HOOK == 1) {
-          ByHash o;
-          o.base = op.base;
-          hk[k] = link_roots(arena, ru, rv, op.n, flags, o);
-        } else if (HOOK == 2) {
-          hk[k] = link_roots_rank(arena, ru, rv, op.n, flags);
-        } else {
-          hk[k] = link_roots(arena, ru, rv, op.n, flags, ById{});
-        }
+        if (HOOK == 1) hk[k] = link_roots(parent, ru, rv, op.n, flags, ByHash{});
+        else if (HOOK == 2) hk[k] = link_roots_rank(parent, ru, rv, op.n, flags);
+        else hk[k] = link_roots(parent, ru, rv, op.n, flags, ById{});
         if (hk[k] >= 0) ++nh;
       }
     }
@@ -105,7 +102,7 @@ __device__ __forceinline__ void pool_tile(const OpDesc& op, uint32_t t, int32_t*
       unsigned pos = block_reserve(nh, hooked_ctl, wave_off, blk);
 #pragma unroll
       for (int k = 0; k < ITEMS; ++k)
-        if (hk[k] >= 0) hooked[pos++] = hk[k];
+        if (hk[k] >= 0) hooked[pos++] = make_int2(op.base, hk[k]);
     }
   } else {
 #pragma unroll
@@ -117,8 +114,8 @@ __device__ __forceinline__ void pool_tile(const OpDesc& op, uint32_t t, int32_t*
       } else if (e[k].x == e[k].y) {
         a = 1;
       } else {
-        const int32_t ru = find_root<HALVE_Q, R>(arena, op.base + e[k].x, op.n, flags);
-        const int32_t rv = find_root<HALVE_Q, R>(arena, op.base + e[k].y, op.n, flags);
+        const int32_t ru = find_root<HALVE_Q, R>(parent, e[k].x, op.n, flags);
+        const int32_t rv = find_root<HALVE_Q, R>(parent, e[k].y, op.n, flags);
         a = ru == rv;
       }
       if (i < op.count) op.out[i] = a;
@@ -129,7 +126,7 @@ __device__ __forceinline__ void pool_tile(const OpDesc& op, uint32_t t, int32_t*
 template <int ITEMS, int HOOK, bool RECORD, bool HALVE_Q>
 __global__ void k_pool_phase(const OpDesc* __restrict__ ops, int nops, uint32_t ntiles,
                              int32_t* __restrict__ arena, unsigned long long* __restrict__ glinks,
-                             int* __restrict__ flags, int32_t* __restrict__ hooked,
+                             int* __restrict__ flags, int2* __restrict__ hooked,
                              unsigned* __restrict__ hooked_ctl) {
   __shared__ int wave_off[16];
   __shared__ unsigned blk[2];
@@ -166,20 +163,37 @@ __global__ void k_pool_rounds(const OpDesc* __restrict__ ops, const int32_t* __r
 }
 
 __global__ void k_init_range(int32_t* __restrict__ arena, int32_t base, int32_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t v = (int32_t)i;
-    arena[base + v] = base + v;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    arena[base + i] = (int32_t)i;
+}
+
+// Every graph of the pool back to singletons in one pass over the arena:
+// table holds (base, n) of the graphs in use, sorted by base; slot i belongs
+// to the last graph whose base is at most i, if it lies within that graph.
+// Free slots are left as they are.
+__global__ void k_pool_init_all(int32_t* __restrict__ arena, int64_t capacity, const int2* __restrict__ table,
+                                int count) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < capacity;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (table[mid].x <= i) lo = mid; else hi = mid - 1;
+    }
+    const int2 g = table[lo];
+    if (g.x <= i && i < (int64_t)g.x + g.y) arena[i] = (int32_t)(i - g.x);
   }
 }
 
-// Labels of one pool graph, graph-local: id order (root = minimum).
+// Labels of one pool graph: id order (root = minimum).
 __global__ void k_pool_labels_id(int32_t* __restrict__ arena, int32_t base, int32_t n, int32_t* __restrict__ out,
                                  int* __restrict__ flags) {
+  int32_t* parent = arena + base;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const int32_t v = (int32_t)i;
-    const int32_t r = find_halve(arena, base + v, n, flags);
-    if (ld(arena + base + v) != r) st(arena + base + v, r);
-    out[v] = r - base;
+    const int32_t r = find_halve(parent, v, n, flags);
+    if (ld(parent + v) != r) st(parent + v, r);
+    out[v] = r;
   }
 }
 
@@ -188,32 +202,43 @@ __global__ void k_pool_labels_id(int32_t* __restrict__ arena, int32_t base, int3
 template <bool R>
 __global__ void k_pool_labels_min(int32_t* __restrict__ arena, int32_t base, int32_t n, int32_t* __restrict__ out,
                                   int* __restrict__ flags) {
+  int32_t* parent = arena + base;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const int32_t v = (int32_t)i;
-    const int32_t r = find_halve<R>(arena, base + v, n, flags);
-    if (r == base + v) continue;
-    if (ld(arena + base + v) != r) st(arena + base + v, r);
-    if (ld(out + (r - base)) > v) atomicMin(out + (r - base), v);  // see k_labels_min
+    const int32_t r = find_halve<R>(parent, v, n, flags);
+    if (r == v) continue;
+    if (ld(parent + v) != r) st(parent + v, r);
+    if (ld(out + r) > v) atomicMin(out + r, v);  // see k_labels_min
   }
 }
 
 template <bool R>
 __global__ void k_pool_labels_gather(const int32_t* __restrict__ arena, int32_t base, int32_t n,
                                      int32_t* __restrict__ out, int* __restrict__ flags) {
+  const int32_t* parent = arena + base;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const int32_t v = (int32_t)i;
-    out[v] = out[find_read<R>(arena, base + v, n, flags) - base];
+    out[v] = out[find_read<R>(parent, v, n, flags)];
   }
 }
 
-// Image conversion for save / load: arena ids <-> graph-local ids.  Done in
-// unsigned arithmetic: under union by rank a root's word carries its rank in
-// the top bits, and the id below them (local id + base < 2^kRankShift) never
-// carries into or borrows from them.
-__global__ void k_to_local(const int32_t* __restrict__ arena, int32_t base, int32_t n, int32_t* __restrict__ out) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t v = (int32_t)i;
-    out[v] = (int32_t)((uint32_t)arena[base + v] - (uint32_t)base);
+// Compress the paths of the roots the last round linked, each entry (graph
+// base, local id); the last block clears the list's count.
+template <bool R>
+__global__ void k_pool_compress_hooked(int32_t* __restrict__ arena, const int2* __restrict__ hooked,
+                                       unsigned* __restrict__ ctl, int32_t cap, int* __restrict__ flags) {
+  const unsigned L = __hip_atomic_load(ctl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < L; i += gridDim.x * blockDim.x) {
+    const int2 h = hooked[i];
+    compress_path<R>(arena + h.x, h.y, cap, flags);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned done = __hip_atomic_fetch_add(ctl + 1, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (done == gridDim.x - 1) {
+      __hip_atomic_store(ctl, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(ctl + 1, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
   }
 }
 
@@ -242,11 +267,48 @@ __global__ void k_check_image(const int32_t* __restrict__ img, int32_t n, unsign
   }
 }
 
-__global__ void k_place(const int32_t* __restrict__ img, int32_t base, int32_t n, int32_t* __restrict__ arena) {
+// Check of a union-by-rank image (graph-local ids, a root's rank in the bits
+// above kRankShift), which keeps no order to test edge by edge:
+//   init    every entry in range, rank bits only on roots; r[v] = parent id;
+//           res[0] += bad entries, res[1] += roots
+//   jump    r[v] = r[r[v]] (an ancestor twice as far up, or the root); an
+//           out-of-range r[v] is left alone, so a bad image cannot send a
+//           read out of bounds
+//   verify  after 32 jumps every vertex must have reached a root (no path is
+//           2^32 long), otherwise the image holds a cycle: res[0] += 1
+__global__ void k_rank_image_init(const int32_t* __restrict__ img, int32_t n, int32_t* __restrict__ r,
+                                  unsigned long long* __restrict__ res) {
+  unsigned long long bad = 0, roots = 0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t v = (int32_t)i;
-    arena[base + v] = (int32_t)((uint32_t)img[v] + (uint32_t)base);
+    const int32_t v = (int32_t)i, w = img[v], q = w & kIdMask;
+    if (q >= n || (w != q && q != v)) ++bad;
+    roots += q == v;
+    r[v] = q;
   }
+  bad = (unsigned long long)wave_sum((int)bad);
+  roots = (unsigned long long)wave_sum((int)roots);
+  if ((threadIdx.x & 63) == 0) {
+    if (bad) atomicAdd(res, bad);
+    if (roots) atomicAdd(res + 1, roots);
+  }
+}
+
+__global__ void k_rank_image_jump(int32_t* __restrict__ r, int32_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t q = r[i];
+    if ((uint32_t)q < (uint32_t)n) r[i] = r[q];
+  }
+}
+
+__global__ void k_rank_image_verify(const int32_t* __restrict__ img, const int32_t* __restrict__ r, int32_t n,
+                                    unsigned long long* __restrict__ res) {
+  unsigned long long bad = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t q = r[i];
+    if ((uint32_t)q >= (uint32_t)n || (img[q] & kIdMask) != q) ++bad;
+  }
+  bad = (unsigned long long)wave_sum((int)bad);
+  if ((threadIdx.x & 63) == 0 && bad) atomicAdd(res, bad);
 }
 
 }  // namespace

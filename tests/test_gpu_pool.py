@@ -149,7 +149,8 @@ def test_pool_gaps_eviction_and_images(cc):
 def test_pool_rank_images_and_limits(cc):
     """Union by rank in a pool: a graph's image carries ranks in its roots'
     words; it round-trips through another slot and through a standalone
-    graph, a cyclic image is refused, and rank needs ids below 2^27."""
+    graph, a cyclic image is refused, and rank needs graphs of at most 2^27
+    vertices (the arena may be larger)."""
     pool = cc.Pool(9000, 4, hook=2)
     a = pool.add(3000)
     b = pool.add(3000)
@@ -184,10 +185,17 @@ def test_pool_rank_images_and_limits(cc):
     np.testing.assert_array_equal(pool.labels(c).cpu().numpy(), ref.labels())
     assert pool.sync() == cc.cc.CC_OK
     pool.close()
-    big = cc.Pool((1 << 27) + 1, 2)
+    # the rank bits limit each graph to 2^27 vertices, not the arena
+    big = cc.Pool((1 << 27) + 2, 2, hook=2)
     with pytest.raises(cc.CCError) as ei:
-        big.set_option("hook", 2)
+        big.add((1 << 27) + 1)
     assert ei.value.code == cc.cc.CC_EINVAL
+    h = big.add(1 << 27)
+    k = big.add(2)
+    big.run([(k, cc.UPDATE, dev([[0, 1]]), None), (h, cc.UPDATE, dev([[0, (1 << 27) - 1], [5, 6]]), None)])
+    assert big.num_components(k) == 1 and big.num_components(h) == (1 << 27) - 2
+    lab = big.labels(h)
+    assert int(lab[(1 << 27) - 1]) == 0 and int(lab[6]) == 5
     big.close()
 
 
