@@ -60,6 +60,7 @@ struct cc_pool {
   unsigned* bar = nullptr;              // device-wide barrier of the one-launch form
   int2* table = nullptr;                // (base, n) of the graphs in use, for cc_pool_reset_all
   std::vector<int2> table_host;
+  bool table_stale = true;              // graphs added or removed since the table was uploaded
   RingSlot ring[kRing];
   int ring_next = 0;
   cc::Tuning tune;
@@ -349,6 +350,7 @@ extern "C" int cc_pool_add(cc_pool* p, int64_t n, int32_t* id) {
   g.base = base;
   g.n = n;
   g.used = true;
+  p->table_stale = true;
   hipLaunchKernelGGL(k_init_range, dim3(blocks_for(n, 256, 4096)), dim3(256), 0, p->stream, p->arena,
                      (int32_t)base, (int32_t)n);
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, p->stream, p->glinks + (size_t)slot * kPoolLinkStride, 1);
@@ -362,6 +364,7 @@ extern "C" int cc_pool_remove(cc_pool* p, int32_t id) {
   PoolGraph& g = p->graphs[(size_t)id];
   give_gap(p, g.base, g.n);
   g = PoolGraph();
+  p->table_stale = true;
   return CC_OK;
 }
 
@@ -380,14 +383,20 @@ extern "C" int cc_pool_reset_all(cc_pool* p) {
   if (!p) return CC_EINVAL;
   DeviceGuard dg(p->device);
   std::vector<int2>& t = p->table_host;
-  t.clear();
-  for (const auto& g : p->graphs)
-    if (g.used) t.push_back(make_int2((int32_t)g.base, (int32_t)g.n));
-  std::sort(t.begin(), t.end(), [](const int2& a, const int2& b) { return a.x < b.x; });
+  if (p->table_stale) {
+    t.clear();
+    for (const auto& g : p->graphs)
+      if (g.used) t.push_back(make_int2((int32_t)g.base, (int32_t)g.n));
+    std::sort(t.begin(), t.end(), [](const int2& a, const int2& b) { return a.x < b.x; });
+    if (!t.empty()) {
+      // uploaded only when the set of graphs changed; waits so that the
+      // host table may be rebuilt next time
+      HIP_TRY(hipMemcpyAsync(p->table, t.data(), t.size() * sizeof(int2), hipMemcpyHostToDevice, p->stream));
+      HIP_TRY(hipStreamSynchronize(p->stream));
+    }
+    p->table_stale = false;
+  }
   if (!t.empty()) {
-    // the host table is reused by the next call only after this copy has run
-    HIP_TRY(hipMemcpyAsync(p->table, t.data(), t.size() * sizeof(int2), hipMemcpyHostToDevice, p->stream));
-    HIP_TRY(hipStreamSynchronize(p->stream));
     hipLaunchKernelGGL(k_pool_init_all, dim3(blocks_for(p->capacity, 256, 4096)), dim3(256), 0, p->stream, p->arena,
                        p->capacity, p->table, (int)t.size());
   }

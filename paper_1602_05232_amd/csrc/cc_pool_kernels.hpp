@@ -170,18 +170,32 @@ __global__ void k_init_range(int32_t* __restrict__ arena, int32_t base, int32_t 
 // Every graph of the pool back to singletons in one pass over the arena:
 // table holds (base, n) of the graphs in use, sorted by base; slot i belongs
 // to the last graph whose base is at most i, if it lies within that graph.
-// Free slots are left as they are.
+// A block takes chunks of 16 * blockDim.x slots; one binary search per chunk
+// finds the graph of its first slot, and each thread steps forward from
+// there as its slots move up.  Free slots are left as they are.
 __global__ void k_pool_init_all(int32_t* __restrict__ arena, int64_t capacity, const int2* __restrict__ table,
                                 int count) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < capacity;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    int lo = 0, hi = count - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (table[mid].x <= i) lo = mid; else hi = mid - 1;
+  __shared__ int first;
+  const int64_t chunk = (int64_t)blockDim.x * 16;
+  for (int64_t c0 = (int64_t)blockIdx.x * chunk; c0 < capacity; c0 += (int64_t)gridDim.x * chunk) {
+    if (threadIdx.x == 0) {
+      int lo = 0, hi = count - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (table[mid].x <= c0) lo = mid; else hi = mid - 1;
+      }
+      first = lo;
     }
-    const int2 g = table[lo];
-    if (g.x <= i && i < (int64_t)g.x + g.y) arena[i] = (int32_t)(i - g.x);
+    __syncthreads();
+    int g = first;
+    for (int k = 0; k < 16; ++k) {
+      const int64_t i = c0 + (int64_t)k * blockDim.x + threadIdx.x;
+      if (i >= capacity) break;
+      while (g + 1 < count && table[g + 1].x <= i) ++g;
+      const int2 t = table[g];
+      if (t.x <= i && i < (int64_t)t.x + t.y) arena[i] = (int32_t)(i - t.x);
+    }
+    __syncthreads();  // first is rewritten for the next chunk
   }
 }
 
