@@ -16,6 +16,7 @@ class OracleExecutor:
         self.item_cost = item_cost
         self.state = {}      # stream -> UnionFind (resident)
         self.evicted = {}    # stream -> UnionFind kept aside (its state image)
+        self.images = {}     # stream -> parent array from a checkpoint, loaded when admitted
         self.nsize = {}
         self.done = {}       # handle -> completion time
         self.next_handle = 0
@@ -49,7 +50,29 @@ class OracleExecutor:
         assert self.can_admit(n)
         self.used += n
         self.nsize[s] = n
-        self.state[s] = self.evicted.pop(s) if s in self.evicted else oracle.UnionFind(n)
+        if s in self.evicted:
+            self.state[s] = self.evicted.pop(s)
+        elif s in self.images:
+            self.state[s] = self._from_image(self.images.pop(s))
+        else:
+            self.state[s] = oracle.UnionFind(n)
+
+    # checkpoint / restore: an image is a stream's parent array; restoring
+    # rebuilds a union-find with the same components from its edges (v, parent[v])
+    def checkpoint(self):
+        out = {s: img.copy() for s, img in self.images.items()}
+        for s, uf in list(self.state.items()) + list(self.evicted.items()):
+            out[s] = uf.parents()
+        return out
+
+    def restore(self, images):
+        self.images.update({s: np.asarray(img, np.int32).copy() for s, img in images.items()})
+
+    @staticmethod
+    def _from_image(img):
+        uf = oracle.UnionFind(len(img))
+        uf.bulk_update(np.stack([np.arange(len(img), dtype=np.int32), img], 1))
+        return uf
 
     def evict(self, s):
         self.evicted[s] = self.state.pop(s)

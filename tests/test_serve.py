@@ -101,3 +101,32 @@ def test_serial_baseline_is_fifo(built_libs):
     assert max(sch.round_sizes) == 1 and ex.max_concurrent == 1
     order = [s for (s, k, t) in ex.log]
     assert order == [r.stream for r in sorted(done, key=lambda r: r.arrival)]
+
+
+def test_crash_mid_trace_and_replay_from_checkpoint(built_libs):
+    """The executor is lost half way through a trace (the scheduler and every
+    resident state with it).  A new executor takes the last checkpoint's
+    images, the requests after the checkpoint are replayed, and every answer
+    equals that of the uninterrupted run, under a budget that evicts."""
+    ns, reqs = make_trace(S=10, R=400, seed=19, nmax=1 << 9)
+    want, _ = expected_answers(ns, reqs)
+    cut = 200
+    budget = max(ns) * 3
+    ex = OracleExecutor(budget)
+    done = Scheduler(ex, ns, max_inflight=2).run(fresh(reqs[:cut]))
+    images = ex.checkpoint()
+    # requests after the checkpoint that the lost executor had started are
+    # simply replayed; nothing of its state survives but the images
+    Scheduler(ex, ns, max_inflight=2).run(fresh(reqs[cut:cut + 50]))
+    del ex
+    ex2 = OracleExecutor(budget)
+    ex2.restore(images)
+    t0 = min(r.arrival for r in reqs[cut:])
+    rest = fresh(reqs[cut:])
+    for r in rest:
+        r.arrival -= t0
+    done += Scheduler(ex2, ns, max_inflight=2).run(rest)
+    got = {r.rid: r.out for r in done if r.kind == QUERY}
+    assert set(got) == set(want)
+    for rid, w in want.items():
+        np.testing.assert_array_equal(got[rid], w, err_msg="request %d" % rid)
