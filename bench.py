@@ -51,8 +51,8 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# sources of the update kernel: a change to either voids stored counter readings
-KERNEL_SOURCES = ("uf_device.hpp", "cc_kernels.hpp")
+# sources of the update kernel: a change to any voids stored counter readings
+KERNEL_SOURCES = ("uf_device.hpp", "cc_kernels.hpp", "cc_member_kernels.hpp", "cc_grid.hpp")
 
 
 def source_digest() -> str:
@@ -273,6 +273,23 @@ def run_rmat(args):
             "note": "E_roof = 1/(2/G + 8/B_s): two random parent reads and 8 streamed bytes per edge"}
         log("gather roofline: G(n)=%.3g/s G(2^30)=%.3g/s B_s=%.1f GB/s E_roof=%.3g e/s frac=%.3f"
             % (G, Gbig, Bs / 1e9, Eroof, upd_rate / Eroof))
+        if opts.get("filter", 0):
+            # ceilings of the membership filter's fast paths: an edge settled
+            # by two bitmap reads, a query by four (membership and touched
+            # words of both ends), each plus its 8 streamed bytes
+            words = (s.n + 31) // 32
+            Gb = roofline.gather_rate(words)
+            Ef = 1.0 / (2.0 / Gb + 8.0 / Bs)
+            Qf = 1.0 / (4.0 / Gb + 8.0 / Bs)
+            res["gather_roofline"]["filter"] = {
+                "bitmap_words": words, "G_gathers_per_s_table_bitmap": Gb,
+                "E_filter_roof_edges_per_s": Ef, "update_frac_of_filter_roof": upd_rate / Ef,
+                "Q_filter_roof_per_s": Qf, "query_frac_of_filter_roof": qry_rate / Qf,
+                "note": "ceiling if every edge (query) were settled by the bitmaps: "
+                        "1/(2/G_b + 8/B_s) per edge, 1/(4/G_b + 8/B_s) per query, G_b = gathers/s "
+                        "from a table of the bitmap's size"}
+            log("filter roofline: G(bitmap)=%.3g/s E_f=%.3g e/s (frac %.3f) Q_f=%.3g q/s (frac %.3f)"
+                % (Gb, Ef, upd_rate / Ef, Qf, qry_rate / Qf))
     g.close()
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline([s], args.cpu_budget)

@@ -105,7 +105,20 @@ enum cc_option {
   /* Pools only (cc_pool_run): 1 = all rounds of a run in one cooperative
    * launch, separated by device-wide barriers, instead of one launch per
    * round; no linked-root compression in that form.  Default 0. */
-  CC_OPT_ONE_LAUNCH = 11
+  CC_OPT_ONE_LAUNCH = 11,
+  /* Membership filter of the largest component: a bitmap (n / 8 bytes of
+   * device memory) of vertices proven connected to an anchor vertex, chosen
+   * as the root most sampled minibatch endpoints lead to.  1 = under the
+   * fused schedule an edge whose endpoints are both in it is dropped without
+   * a find (it could only join a component with itself); 2 = that, and
+   * Bulk-Query also answers such a pair 1 without a find (and adds the
+   * endpoints its finds prove connected).  Bits are set only from proofs
+   * (a find that meets the anchor's root, or an edge joined to a member), so
+   * results are unchanged.  Choosing the anchor costs one single-block launch
+   * (and a clearing launch) before update calls 0, 1, 2, 4, 8, ... and every
+   * 64th call after a reset or load.  The split and contracting schedules,
+   * Bulk-Find and cc_bulk_stream neither use nor update it.  Default 0. */
+  CC_OPT_FILTER = 12
 };
 
 /* Create a graph on vertices [0, n), 1 <= n <= 2^31 - 1, every vertex its own
@@ -184,6 +197,18 @@ int cc_num_components(cc_graph* g, int64_t* out);
  * the parent array.  Equals cc_num_components; kept as an independent check.
  * Waits for the stream. */
 int cc_count_roots(cc_graph* g, int64_t* out);
+
+/* State of the membership filter (CC_OPT_FILTER), for checks.  *anchor gets
+ * the anchor vertex (-1 if none, or if the filter has not run since the
+ * last reset or load).  *touched_complete gets 1 while every update since
+ * the last reset went through the filtered fused form, so that the touched
+ * bitmap is complete, else 0.  Unless bits is NULL, it gets 2 * ceil(n / 32)
+ * HOST uint32 words: the membership bitmap, then the touched bitmap, vertex
+ * v at bit v % 32 of word v / 32 of each (all zero if the filter has never
+ * run).  Every vertex in the membership bitmap is connected to the anchor;
+ * while touched_complete is 1, every vertex in neither bitmap is alone in
+ * its component.  Waits for the stream. */
+int cc_filter_state(cc_graph* g, int32_t* anchor, int32_t* touched_complete, uint32_t* bits);
 
 /* Wait for all work issued on g's stream; then report, once, a skipped id
  * (CC_ERANGE) or a corrupt forest (CC_ECORRUPT) latched since the last

@@ -18,11 +18,12 @@ LIB_PATH = os.path.join(_HERE, "libcc.so")
 CC_OK, CC_EINVAL, CC_ENOMEM, CC_ERANGE, CC_EDEVICE, CC_ECORRUPT = 0, -1, -2, -3, -4, -5
 OPT_UPDATE_MODE, OPT_BLOCK, OPT_ITEMS, OPT_QUERY_HALVING = 1, 2, 3, 4
 OPT_COMPRESS_EVERY, OPT_HOOK, OPT_GRID_CAP, OPT_COMPRESS_LINKED, OPT_SPIN_LIMIT, OPT_FIND = 5, 6, 7, 8, 9, 10
-OPT_ONE_LAUNCH = 11
+OPT_ONE_LAUNCH, OPT_FILTER = 11, 12
 _OPT_NAMES = {"update_mode": OPT_UPDATE_MODE, "block": OPT_BLOCK, "items": OPT_ITEMS,
               "query_halving": OPT_QUERY_HALVING, "compress_every": OPT_COMPRESS_EVERY,
               "hook": OPT_HOOK, "grid_cap": OPT_GRID_CAP, "compress_linked": OPT_COMPRESS_LINKED,
-              "spin_limit": OPT_SPIN_LIMIT, "find": OPT_FIND, "one_launch": OPT_ONE_LAUNCH}
+              "spin_limit": OPT_SPIN_LIMIT, "find": OPT_FIND, "one_launch": OPT_ONE_LAUNCH,
+              "filter": OPT_FILTER}
 
 # Every symbol include/cc.h declares, with (restype, argtypes).
 _vp, _i64, _i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
@@ -40,6 +41,7 @@ SIGNATURES = {
     "cc_labels": (_i32, [_vp, _vp]),
     "cc_num_components": (_i32, [_vp, ctypes.POINTER(_i64)]),
     "cc_count_roots": (_i32, [_vp, ctypes.POINTER(_i64)]),
+    "cc_filter_state": (_i32, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), _vp]),
     "cc_sync": (_i32, [_vp]),
     "cc_state_bytes": (_i64, [_vp]),
     "cc_save": (_i32, [_vp, _vp]),
@@ -245,6 +247,17 @@ class Graph:
         v = ctypes.c_int64()
         _check(lib().cc_count_roots(self._h, ctypes.byref(v)))
         return v.value
+
+    def filter_state(self):
+        """(anchor, touched_complete, membership bitmap, touched bitmap) of the
+        membership filter, the bitmaps as numpy uint32 arrays of ceil(n/32)
+        words; waits for the stream."""
+        import numpy as np
+        a, c = ctypes.c_int32(), ctypes.c_int32()
+        w = (self.n + 31) // 32
+        bits = np.zeros(2 * w, np.uint32)
+        _check(lib().cc_filter_state(self._h, ctypes.byref(a), ctypes.byref(c), bits.ctypes.data))
+        return a.value, bool(c.value), bits[:w], bits[w:]
 
     def sync(self) -> int:
         """Wait for the stream; returns CC_OK, CC_ERANGE or CC_ECORRUPT

@@ -54,6 +54,7 @@ struct Tuning {
   int64_t spin_limit = 1 << 24;  // CC_OPT_SPIN_LIMIT
   int find = 0;                  // CC_OPT_FIND
   int one_launch = 0;            // CC_OPT_ONE_LAUNCH (pools)
+  int filter = 0;                // CC_OPT_FILTER
 };
 
 inline bool set_tuning(Tuning* t, int key, int64_t v) {
@@ -102,6 +103,10 @@ inline bool set_tuning(Tuning* t, int key, int64_t v) {
       if (v != 0 && v != 1) return false;
       t->one_launch = (int)v;
       return true;
+    case CC_OPT_FILTER:
+      if (v < 0 || v > 2) return false;
+      t->filter = (int)v;
+      return true;
     default:
       return false;
   }
@@ -120,6 +125,7 @@ inline bool get_tuning(const Tuning* t, int key, int64_t* v) {
     case CC_OPT_SPIN_LIMIT: *v = t->spin_limit; return true;
     case CC_OPT_FIND: *v = t->find; return true;
     case CC_OPT_ONE_LAUNCH: *v = t->one_launch; return true;
+    case CC_OPT_FILTER: *v = t->filter; return true;
     default: return false;
   }
 }

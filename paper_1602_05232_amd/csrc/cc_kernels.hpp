@@ -13,10 +13,14 @@
 //                    path compression of Section 6.1, applied to the roots the
 //                    minibatch touched)
 //   k_query          Algorithm 1: out[i] = find(u_i) == find(v_i)
+// With FILT, the fused update and the query first consult the membership
+// bitmap of the largest component (cc_member_kernels.hpp).
 // (passes over all vertices -- labels, compression, root count -- are in
 // cc_vertex_kernels.hpp)
 #pragma once
 
+#include "cc_grid.hpp"
+#include "cc_member_kernels.hpp"
 #include "uf_device.hpp"
 
 namespace ccdev {
@@ -70,20 +74,121 @@ __device__ __forceinline__ unsigned block_reserve(int cnt, unsigned* counter, in
   return pos;
 }
 
+// Joins the trees of u and v, given parent ids pu and pv read earlier (an
+// earlier read may be stale; it is still an ancestor, which is all a find
+// needs).  Returns the root this call linked under the other tree, or -1.
+// With filt, u and v join the membership bitmap once either is known to be
+// connected to the anchor (bu, bv: their bits as read before).  With a
+// touched bitmap, a link marks the linked root and the vertex it now hangs
+// under: every vertex that has had an edge is a non-root or a root with a
+// child, and became one through such a link.
+template <class Ord>
+__device__ __forceinline__ int32_t settle_edge(int32_t* parent, int32_t u, int32_t v, int32_t pu, int32_t pv,
+                                               int32_t n, int* flags, bool filt, int32_t ra, uint32_t* member,
+                                               bool bu, bool bv, uint32_t* touched) {
+  constexpr bool R = is_ranked<Ord>::value;
+  if (pu == pv || pu == v || pv == u) {  // already one tree
+    if (filt) member_join(member, u, v, bu, bv, bu || bv || pu == ra || pv == ra);
+    return -1;
+  }
+  const int32_t ru = find_halve_from<R>(parent, u, pu, n, flags);
+  const int32_t rv = find_halve_from<R>(parent, v, pv, n, flags);
+  int32_t w = -1;
+  const int32_t h = ru != rv ? link(parent, ru, rv, n, flags, Ord{}, &w) : -1;
+  if (filt) member_join(member, u, v, bu, bv, bu || bv || ru == ra || rv == ra);
+  if (touched && h >= 0) {
+    member_add(touched, h);
+    // w now has a child.  A hub root is the winning side of many links; its
+    // bit is read from L2 first so that only the first few send an atomic.
+    if (!member_bit(member_word_l2(touched, w), w)) member_add(touched, w);
+  }
+  return h;
+}
+
+// Filtered form: edges the bitmap does not settle wait in a per-block LDS
+// list, and the block settles the list when it is nearly full and at the
+// end.  A few percent of open edges would otherwise put one slow chain of
+// dependent reads (parents, finds, link) into almost every wavefront; the
+// list gathers them, so the wavefronts that only stream edges and test
+// bits run at the speed of those reads.  List entries carry the two bits
+// read at scan time in their sign bits (ids are below 2^31).  The drain also
+// keeps the touched bitmap (settle_edge).
+constexpr int kDeferCap = 2048;       // entries per block (16 KB of LDS)
+constexpr int kDeferTileMax = 1024;   // largest blockDim.x * ITEMS of the filtered form
+constexpr int kDrainItems = 4;        // listed edges per thread per pass of the drain
+
+template <class Ord, bool RECORD>
+__device__ int drain_list(int32_t* parent, const int2* list, int nd, int32_t n, int* flags, int32_t ra,
+                          uint32_t* member, uint32_t* touched, int32_t* hooked, unsigned* hooked_ctl, int* wave_off,
+                          unsigned* blk) {
+  constexpr bool R = is_ranked<Ord>::value;
+  const int B = blockDim.x;
+  int links = 0;
+  for (int base = 0; base < nd; base += B * kDrainItems) {  // same trip count in every thread
+    int2 p[kDrainItems];
+    int32_t pu[kDrainItems], pv[kDrainItems];
+    unsigned open = 0;
+#pragma unroll
+    for (int k = 0; k < kDrainItems; ++k) {
+      const int i = base + k * B + (int)threadIdx.x;
+      pu[k] = pv[k] = 0;
+      p[k] = make_int2(0, 0);
+      if (i < nd) {
+        p[k] = list[i];
+        open |= 1u << k;
+        pu[k] = ldp<R>(parent + (p[k].x & 0x7fffffff));
+        pv[k] = ldp<R>(parent + (p[k].y & 0x7fffffff));
+      }
+    }
+    int32_t hk[kDrainItems];
+    int nh = 0;
+#pragma unroll
+    for (int k = 0; k < kDrainItems; ++k) {
+      hk[k] = -1;
+      if (!((open >> k) & 1u)) continue;
+      const int32_t u = p[k].x & 0x7fffffff, v = p[k].y & 0x7fffffff;
+      hk[k] = settle_edge<Ord>(parent, u, v, pu[k], pv[k], n, flags, ra >= 0, ra, member, p[k].x < 0, p[k].y < 0,
+                               touched);
+      if (hk[k] >= 0) ++nh;
+    }
+    links += nh;
+    if (RECORD) {
+      unsigned pos = block_reserve(nh, hooked_ctl, wave_off, blk);
+#pragma unroll
+      for (int k = 0; k < kDrainItems; ++k)
+        if (hk[k] >= 0) hooked[pos++] = hk[k];
+    }
+  }
+  return links;
+}
+
 // One tile = blockDim.x * ITEMS consecutive edges; item k of thread t is edge
 // tile_start + k * blockDim.x + t, so every load instruction of a wavefront
-// reads 512 contiguous bytes.  With RECORD, every root this kernel links under
-// another tree is appended to `hooked` (count in hooked_ctl[0]) for the
-// compression pass that follows.
-template <int ITEMS, class Ord, bool RECORD>
+// reads 512 contiguous bytes.  A tile goes in phases so that the loads of all
+// its items are in flight together rather than one item's after another's:
+// membership words (FILT), then the parents of the items still open, then
+// finds and links item by item.  With RECORD, every root this kernel links
+// under another tree is appended to `hooked` (count in hooked_ctl[0]) for the
+// compression pass that follows.  With FILT (blockDim.x * ITEMS at most
+// kDeferTileMax), an edge whose endpoints are both in the membership bitmap
+// is dropped before any parent read, the others go through the block's list
+// (above), and the endpoints of every edge joined (or found joined) are added
+// to the bitmap once one of them is known to be connected to the anchor.
+template <int ITEMS, class Ord, bool RECORD, bool FILT>
 __global__ void k_update_fused(int32_t* __restrict__ parent, const int2* __restrict__ edges, int64_t m,
                                int32_t n, unsigned long long* __restrict__ slots, int* __restrict__ flags,
-                               int32_t* __restrict__ hooked, unsigned* __restrict__ hooked_ctl) {
+                               int32_t* __restrict__ hooked, unsigned* __restrict__ hooked_ctl,
+                               const int32_t* __restrict__ member_ctl, uint32_t* __restrict__ member) {
   constexpr bool R = is_ranked<Ord>::value;
-  __shared__ int wave_off[16];
+  __shared__ int wave_off[17];
   __shared__ unsigned blk[2];
+  __shared__ int2 list[FILT ? kDeferCap : 1];
   const int64_t tile = (int64_t)blockDim.x * ITEMS;
+  const int64_t member_words = ((int64_t)n + 31) >> 5;  // the touched bitmap follows the membership bitmap
   int links = 0;
+  const int32_t ra = FILT ? anchor_root<R>(parent, member_ctl, n, flags) : -1;
+  const bool filt = FILT && ra >= 0;
+  int nd = 0;  // FILT: entries in the block's list (the same in every thread)
   for (int64_t t0 = (int64_t)blockIdx.x * tile; t0 < m; t0 += (int64_t)gridDim.x * tile) {
     int2 e[ITEMS];
 #pragma unroll
@@ -91,25 +196,72 @@ __global__ void k_update_fused(int32_t* __restrict__ parent, const int2* __restr
       const int64_t i = t0 + (int64_t)k * blockDim.x + threadIdx.x;
       e[k] = i < m ? edges[i] : make_int2(0, 0);  // padding: a self-loop on vertex 0
     }
-    int32_t hk[ITEMS];
-    int nh = 0;
+    uint32_t mu[ITEMS], mv[ITEMS];
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
-      hk[k] = -1;
+      mu[k] = mv[k] = 0u;
+      if (filt && in_range(e[k], n)) {
+        mu[k] = member_word(member, e[k].x);
+        mv[k] = member_word(member, e[k].y);
+      }
+    }
+    if (FILT) {
+      int c = 0;
+#pragma unroll
+      for (int k = 0; k < ITEMS; ++k) {
+        if (!in_range(e[k], n)) {
+          raise_flag(flags, kFlagRange);
+          e[k] = make_int2(0, 0);
+          continue;
+        }
+        const int32_t u = e[k].x, v = e[k].y;
+        const bool bu = filt && member_bit(mu[k], u), bv = filt && member_bit(mv[k], v);
+        if (u == v || (bu && bv)) {
+          e[k] = make_int2(0, 0);
+          continue;
+        }
+        e[k] = make_int2(bu ? (int32_t)((uint32_t)u | 0x80000000u) : u, bv ? (int32_t)((uint32_t)v | 0x80000000u) : v);
+        ++c;
+      }
+      int total;
+      int at = nd + block_scan(c, &total, wave_off);
+#pragma unroll
+      for (int k = 0; k < ITEMS; ++k)
+        if (e[k].x != e[k].y) list[at++] = e[k];
+      nd += total;
+      if (nd > kDeferCap - (int)tile) {
+        __syncthreads();  // the list is complete
+        links += drain_list<Ord, RECORD>(parent, list, nd, n, flags, ra, member, member + member_words,
+                                         hooked, hooked_ctl, wave_off, blk);
+        __syncthreads();  // every entry has been read before the list is refilled
+        nd = 0;
+      }
+      continue;
+    }
+    int32_t pu[ITEMS], pv[ITEMS];
+    unsigned open = 0;  // bit k: item k needs its roots
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      pu[k] = pv[k] = 0;
       if (!in_range(e[k], n)) {
         raise_flag(flags, kFlagRange);
         continue;
       }
       const int32_t u = e[k].x, v = e[k].y;
       if (u == v) continue;
-      const int32_t pu = ldp<R>(parent + u), pv = ldp<R>(parent + v);
-      if (pu == pv || pu == v || pv == u) continue;  // already one tree
-      const int32_t ru = find_halve_from<R>(parent, u, pu, n, flags);
-      const int32_t rv = find_halve_from<R>(parent, v, pv, n, flags);
-      if (ru != rv) {
-        hk[k] = link(parent, ru, rv, n, flags, Ord{});
-        if (hk[k] >= 0) ++nh;
-      }
+      open |= 1u << k;
+      pu[k] = ldp<R>(parent + u);
+      pv[k] = ldp<R>(parent + v);
+    }
+    int32_t hk[ITEMS];
+    int nh = 0;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      hk[k] = -1;
+      if (!((open >> k) & 1u)) continue;
+      hk[k] = settle_edge<Ord>(parent, e[k].x, e[k].y, pu[k], pv[k], n, flags, false, -1, member, false, false,
+                               nullptr);
+      if (hk[k] >= 0) ++nh;
     }
     links += nh;
     if (RECORD) {
@@ -118,6 +270,11 @@ __global__ void k_update_fused(int32_t* __restrict__ parent, const int2* __restr
       for (int k = 0; k < ITEMS; ++k)
         if (hk[k] >= 0) hooked[pos++] = hk[k];
     }
+  }
+  if (FILT && nd > 0) {
+    __syncthreads();
+    links += drain_list<Ord, RECORD>(parent, list, nd, n, flags, ra, member, member + member_words, hooked,
+                                     hooked_ctl, wave_off, blk);
   }
   count_links(slots, links);
 }
@@ -249,10 +406,22 @@ __global__ void k_compress_hooked(int32_t* __restrict__ parent, const int32_t* _
   }
 }
 
-template <int ITEMS, bool HALVE, bool R = false>
+// Same phases as the fused update: membership and touched words (FILT), then
+// the parents of the pairs still open, then the finds.  With FILT, a pair
+// whose endpoints are both in the membership bitmap answers 1 without a
+// find; while the touched bitmap is complete, a pair with an endpoint in
+// neither bitmap answers 0 without a find; and an endpoint whose find meets
+// the anchor's root (or that is found joined to a member) is added to the
+// membership bitmap.
+template <int ITEMS, bool HALVE, bool R, bool FILT>
 __global__ void k_query(int32_t* __restrict__ parent, const int2* __restrict__ pairs, int64_t q, int32_t n,
-                        uint8_t* __restrict__ out, int* __restrict__ flags) {
+                        uint8_t* __restrict__ out, int* __restrict__ flags, const int32_t* __restrict__ member_ctl,
+                        uint32_t* __restrict__ member) {
   const int64_t tile = (int64_t)blockDim.x * ITEMS;
+  const int32_t ra = FILT ? anchor_root<R>(parent, member_ctl, n, flags) : -1;
+  const bool filt = FILT && ra >= 0;
+  const bool lone = FILT && touched_complete(member_ctl);  // the touched bitmap may prove a vertex alone
+  const uint32_t* touched = FILT ? member + (((int64_t)n + 31) >> 5) : nullptr;
   for (int64_t t0 = (int64_t)blockIdx.x * tile; t0 < q; t0 += (int64_t)gridDim.x * tile) {
     int2 e[ITEMS];
 #pragma unroll
@@ -260,20 +429,61 @@ __global__ void k_query(int32_t* __restrict__ parent, const int2* __restrict__ p
       const int64_t i = t0 + (int64_t)k * blockDim.x + threadIdx.x;
       e[k] = i < q ? pairs[i] : make_int2(0, 0);
     }
+    uint32_t mu[ITEMS], mv[ITEMS], tu[ITEMS], tv[ITEMS];
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      mu[k] = mv[k] = tu[k] = tv[k] = 0u;
+      if ((filt || lone) && in_range(e[k], n)) {
+        mu[k] = member_word(member, e[k].x);
+        mv[k] = member_word(member, e[k].y);
+      }
+      if (lone && in_range(e[k], n)) {
+        tu[k] = member_word(touched, e[k].x);
+        tv[k] = member_word(touched, e[k].y);
+      }
+    }
+    int32_t pu[ITEMS], pv[ITEMS];
+    uint8_t a[ITEMS];
+    unsigned open = 0;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      pu[k] = pv[k] = 0;
+      a[k] = 0;
+      if (!in_range(e[k], n)) {
+        raise_flag(flags, kFlagRange);
+        continue;
+      }
+      const int32_t u = e[k].x, v = e[k].y;
+      if (u == v || (filt && member_bit(mu[k], u) && member_bit(mv[k], v))) {
+        a[k] = 1;
+        continue;
+      }
+      // a vertex in neither bitmap has never had an edge: alone, so not connected to the other
+      if (lone && ((!member_bit(mu[k], u) && !member_bit(tu[k], u)) || (!member_bit(mv[k], v) && !member_bit(tv[k], v))))
+        continue;
+      open |= 1u << k;
+      pu[k] = ldp<R>(parent + u);
+      pv[k] = ldp<R>(parent + v);
+    }
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      if (!((open >> k) & 1u)) continue;
+      const int32_t u = e[k].x, v = e[k].y;
+      const int32_t ru = find_root_from<HALVE, R>(parent, u, pu[k], n, flags);
+      const int32_t rv = find_root_from<HALVE, R>(parent, v, pv[k], n, flags);
+      a[k] = ru == rv;
+      if (filt) {
+        const bool bu = member_bit(mu[k], u), bv = member_bit(mv[k], v);
+        bool iu = bu || ru == ra, iv = bv || rv == ra;
+        if (a[k]) iu = iv = iu || iv;
+        if (iu && !bu) member_add(member, u);
+        if (iv && !bv) member_add(member, v);
+      }
+    }
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
       const int64_t i = t0 + (int64_t)k * blockDim.x + threadIdx.x;
-      uint8_t a = 0;
-      if (!in_range(e[k], n)) {
-        raise_flag(flags, kFlagRange);
-      } else if (e[k].x == e[k].y) {
-        a = 1;
-      } else {
-        const int32_t ru = find_root<HALVE, R>(parent, e[k].x, n, flags);
-        const int32_t rv = find_root<HALVE, R>(parent, e[k].y, n, flags);
-        a = ru == rv;
-      }
-      if (i < q) out[i] = a;
+      if (i < q) out[i] = a[k];
     }
   }
 }

@@ -16,6 +16,7 @@
 #include "cc_bulkfind_kernels.hpp"
 #include "cc_contract_kernels.hpp"
 #include "cc_stream_kernels.hpp"
+#include "cc_member_kernels.hpp"
 
 using namespace ccdev;
 using cc::blocks_for;
@@ -62,6 +63,10 @@ struct cc_graph {
   BulkFindScratch bf{};          // Bulk-Find scratch (allocated on first use)
   bool bf_ready = false;
   int64_t bf_seg0_entries = 0;   // allocated level-0 entries
+  uint32_t* member = nullptr;    // membership bitmap of the filter, ceil(n / 32) words
+  int32_t* member_ctl = nullptr; // kMemberCtlWords: anchor, clear request
+  int64_t member_calls = 0;      // fused updates since the filter state was last reset
+  bool pristine = true;          // no update or load since creation or the last reset
   int64_t live_cap = 0;
   int64_t updates = 0;
   bool capturing = false;
@@ -141,30 +146,92 @@ int alloc_bulkfind(cc_graph* g) {
   return CC_OK;
 }
 
+int64_t member_words(const cc_graph* g) { return (g->n + 31) / 32; }
+
+// No anchor and both bitmaps empty (kernels only, so it can be captured).
+// touched_complete: 1 for the initial forest (every vertex alone), 0 for a
+// loaded one.
+void member_reset(cc_graph* g, int touched_complete) {
+  const int64_t words = member_words(g);
+  hipLaunchKernelGGL(k_member_ctl_reset, dim3(1), dim3(64), 0, g->stream, g->member_ctl, touched_complete);
+  hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(2 * words, 256, 4096)), dim3(256), 0, g->stream,
+                     (int32_t*)g->member, (int32_t)(2 * words), 0);
+  g->member_calls = 0;
+}
+
+// An update that does not keep the touched bitmap complete is about to run.
+void member_touched_invalid(cc_graph* g) {
+  if (g->member) hipLaunchKernelGGL(k_member_touched_invalid, dim3(1), dim3(64), 0, g->stream, g->member_ctl);
+}
+
+int alloc_member(cc_graph* g) {
+  if (g->member) return CC_OK;
+  // membership bitmap, then touched bitmap
+  if (hipMalloc(&g->member, (size_t)member_words(g) * 8) != hipSuccess ||
+      hipMalloc(&g->member_ctl, kMemberCtlWords * sizeof(int32_t)) != hipSuccess) {
+    (void)hipFree(g->member);
+    g->member = nullptr;
+    g->member_ctl = nullptr;
+    cc_set_error("hipMalloc of the membership filter (n / 4 bytes) failed");
+    return CC_ENOMEM;
+  }
+  member_reset(g, g->pristine ? 1 : 0);
+  HIP_TRY(hipGetLastError());
+  return CC_OK;
+}
+
+// Re-pick the anchor before update calls 0, 1, 2, 4, 8, ... and every 64th.
+template <bool R>
+void member_pick(cc_graph* g, const int2* e, int64_t m) {
+  const int64_t c = g->member_calls++;
+  if ((c & (c - 1)) != 0 && c % 64 != 0) return;
+  hipLaunchKernelGGL(k_anchor_pick<R>, dim3(1), dim3(kPickThreads), 0, g->stream, g->parent, e, m,
+                     (int32_t)g->n, g->member_ctl, g->flags);
+  const int64_t words = member_words(g);
+  hipLaunchKernelGGL(k_member_clear, dim3(blocks_for(words, 256, 256)), dim3(256), 0, g->stream, g->member_ctl,
+                     g->member, words);
+}
+
 int launch_init(cc_graph* g) {
   const unsigned blocks = blocks_for((g->n + 3) / 4, 256, 2048);
   hipLaunchKernelGGL(k_init, dim3(blocks), dim3(256), 0, g->stream, g->parent, g->n);
   hipLaunchKernelGGL(k_zero_u64, dim3(4), dim3(256), 0, g->stream, g->slots, kSlots * kSlotStride);
   if (g->bf_ready) clear_bulkfind(g);
+  if (g->member) member_reset(g, 1);
+  g->pristine = true;
   HIP_TRY(hipGetLastError());
   return CC_OK;
 }
 
-template <int ITEMS, class Ord, bool RECORD>
+template <int ITEMS, class Ord, bool RECORD, bool FILT>
 void launch_fused_t(cc_graph* g, const int2* e, int64_t m) {
   const int B = g->tune.block;
   const unsigned blocks = blocks_for(m, (int64_t)B * ITEMS, g->tune.grid_cap);
-  hipLaunchKernelGGL((k_update_fused<ITEMS, Ord, RECORD>), dim3(blocks), dim3(B), 0, g->stream, g->parent, e,
-                     m, (int32_t)g->n, g->slots, g->flags, g->hooked, g->live_ctl + 2);
+  hipLaunchKernelGGL((k_update_fused<ITEMS, Ord, RECORD, FILT>), dim3(blocks), dim3(B), 0, g->stream, g->parent,
+                     e, m, (int32_t)g->n, g->slots, g->flags, g->hooked, g->live_ctl + 2, g->member_ctl,
+                     g->member);
+}
+
+template <class Ord, bool RECORD, bool FILT>
+void launch_fused_f(cc_graph* g, const int2* e, int64_t m) {
+  int items = cc::pick_items(g->tune.items, m, g->tune.block);
+  while (FILT && items > 1 && g->tune.block * items > kDeferTileMax) items >>= 1;  // a tile fits the list
+  switch (items) {
+    case 1: launch_fused_t<1, Ord, RECORD, FILT>(g, e, m); break;
+    case 2: launch_fused_t<2, Ord, RECORD, FILT>(g, e, m); break;
+    case 8: launch_fused_t<8, Ord, RECORD, FILT>(g, e, m); break;
+    default: launch_fused_t<4, Ord, RECORD, FILT>(g, e, m); break;
+  }
 }
 
 template <class Ord, bool RECORD>
 void launch_fused_r(cc_graph* g, const int2* e, int64_t m) {
-  switch (cc::pick_items(g->tune.items, m, g->tune.block)) {
-    case 1: launch_fused_t<1, Ord, RECORD>(g, e, m); break;
-    case 2: launch_fused_t<2, Ord, RECORD>(g, e, m); break;
-    case 8: launch_fused_t<8, Ord, RECORD>(g, e, m); break;
-    default: launch_fused_t<4, Ord, RECORD>(g, e, m); break;
+  if (g->tune.filter && g->member) {
+    member_pick<is_ranked<Ord>::value>(g, e, m);
+    launch_fused_f<Ord, RECORD, true>(g, e, m);
+  } else {
+    member_touched_invalid(g);
+    launch_fused_f<Ord, RECORD, false>(g, e, m);
   }
 }
 
@@ -204,22 +271,28 @@ void launch_split_o(cc_graph* g, const int2* e, int64_t m) {
                      (int32_t)g->n, g->flags);
 }
 
-template <int ITEMS, bool HALVE, bool R>
+template <int ITEMS, bool HALVE, bool R, bool FILT>
 void launch_query_t(cc_graph* g, const int2* p, int64_t q, uint8_t* out) {
   const int B = g->tune.block;
   const unsigned blocks = blocks_for(q, (int64_t)B * ITEMS, g->tune.grid_cap);
-  hipLaunchKernelGGL((k_query<ITEMS, HALVE, R>), dim3(blocks), dim3(B), 0, g->stream, g->parent, p, q,
-                     (int32_t)g->n, out, g->flags);
+  hipLaunchKernelGGL((k_query<ITEMS, HALVE, R, FILT>), dim3(blocks), dim3(B), 0, g->stream, g->parent, p, q,
+                     (int32_t)g->n, out, g->flags, g->member_ctl, g->member);
+}
+
+template <bool HALVE, bool R, bool FILT>
+void launch_query_f(cc_graph* g, const int2* p, int64_t q, uint8_t* out) {
+  switch (cc::pick_items(g->tune.items, q, g->tune.block)) {
+    case 1: launch_query_t<1, HALVE, R, FILT>(g, p, q, out); break;
+    case 2: launch_query_t<2, HALVE, R, FILT>(g, p, q, out); break;
+    case 8: launch_query_t<8, HALVE, R, FILT>(g, p, q, out); break;
+    default: launch_query_t<4, HALVE, R, FILT>(g, p, q, out); break;
+  }
 }
 
 template <bool HALVE, bool R>
 void launch_query_h(cc_graph* g, const int2* p, int64_t q, uint8_t* out) {
-  switch (cc::pick_items(g->tune.items, q, g->tune.block)) {
-    case 1: launch_query_t<1, HALVE, R>(g, p, q, out); break;
-    case 2: launch_query_t<2, HALVE, R>(g, p, q, out); break;
-    case 8: launch_query_t<8, HALVE, R>(g, p, q, out); break;
-    default: launch_query_t<4, HALVE, R>(g, p, q, out); break;
-  }
+  if (g->tune.filter == 2 && g->member) launch_query_f<HALVE, R, true>(g, p, q, out);
+  else launch_query_f<HALVE, R, false>(g, p, q, out);
 }
 
 unsigned vertex_blocks(const cc_graph* g) { return blocks_for(g->n, 256, 4096); }
@@ -391,6 +464,8 @@ extern "C" int cc_destroy(cc_graph* g) {
   (void)hipFree(g->gbar);
   (void)hipFree(g->hooked);
   (void)hipFree(g->contract_ctl);
+  (void)hipFree(g->member);
+  (void)hipFree(g->member_ctl);
   if (g->bf_ready) free_bulkfind(g);
   delete g;
   return CC_OK;
@@ -433,6 +508,7 @@ extern "C" int cc_reserve(cc_graph* g, int64_t max_batch) {
   }
   DeviceGuard dg(g->device);
   int rc = alloc_hooked(g);
+  if (rc == CC_OK && g->tune.filter) rc = alloc_member(g);
   if (rc != CC_OK) return rc;
   if (g->tune.mode == 2 && max_batch > 0) {
     int64_t grid = 0;
@@ -459,7 +535,10 @@ extern "C" int cc_bulk_update(cc_graph* g, const int32_t* edges, int64_t m) {
   if (m == 0) return CC_OK;
   DeviceGuard dg(g->device);
   const int2* e = reinterpret_cast<const int2*>(edges);
+  const bool was_pristine = g->pristine;
+  g->pristine = false;
   if (g->tune.find == 1) {
+    member_touched_invalid(g);
     int rc = launch_bulk_find<0>(g, e, m, nullptr);
     if (rc == CC_OK) g->updates++;
     return rc;
@@ -478,6 +557,7 @@ extern "C" int cc_bulk_update(cc_graph* g, const int32_t* edges, int64_t m) {
       cc_set_error("cc_bulk_update: the contracting update takes at most 2^31-1 edges per call");
       return CC_EINVAL;
     }
+    member_touched_invalid(g);
     int rc = hashed ? launch_contract_t<ByHash>(g, e, m) : launch_contract_t<ById>(g, e, m);
     if (rc != CC_OK) return rc;
   } else if (g->tune.mode == 1) {
@@ -492,6 +572,7 @@ extern "C" int cc_bulk_update(cc_graph* g, const int32_t* edges, int64_t m) {
     }
     int rc = alloc_live(g, m);
     if (rc != CC_OK) return rc;
+    member_touched_invalid(g);
     if (hashed) launch_split_o<ByHash>(g, e, m);
     else launch_split_o<ById>(g, e, m);
   } else {
@@ -501,6 +582,16 @@ extern "C" int cc_bulk_update(cc_graph* g, const int32_t* edges, int64_t m) {
         return CC_EINVAL;
       }
       int rc = alloc_hooked(g);
+      if (rc != CC_OK) return rc;
+    }
+    if (g->tune.filter && !g->member) {
+      if (g->capturing) {
+        cc_set_error("cc_bulk_update: call cc_reserve before capturing");
+        return CC_EINVAL;
+      }
+      g->pristine = was_pristine;  // this update is the filter's first
+      int rc = alloc_member(g);
+      g->pristine = false;
       if (rc != CC_OK) return rc;
     }
     if (ranked) launch_fused_o<ByRank>(g, e, m);
@@ -599,6 +690,29 @@ extern "C" int cc_count_roots(cc_graph* g, int64_t* out) {
   return CC_OK;
 }
 
+extern "C" int cc_filter_state(cc_graph* g, int32_t* anchor, int32_t* touched_complete, uint32_t* bits) {
+  if (!g || !anchor || !touched_complete) return CC_EINVAL;
+  if (g->capturing) {
+    cc_set_error("call not allowed while capturing");
+    return CC_EINVAL;
+  }
+  DeviceGuard dg(g->device);
+  const size_t words = (size_t)member_words(g);
+  if (!g->member) {
+    *anchor = -1;
+    *touched_complete = 0;
+    if (bits) memset(bits, 0, 2 * words * 4);
+    return CC_OK;
+  }
+  int32_t ctl[kMemberCtlWords];
+  HIP_TRY(hipMemcpyAsync(ctl, g->member_ctl, sizeof(ctl), hipMemcpyDeviceToHost, g->stream));
+  if (bits) HIP_TRY(hipMemcpyAsync(bits, g->member, 2 * words * 4, hipMemcpyDeviceToHost, g->stream));
+  HIP_TRY(hipStreamSynchronize(g->stream));
+  *anchor = ctl[0];
+  *touched_complete = ctl[2];
+  return CC_OK;
+}
+
 extern "C" int cc_sync(cc_graph* g) {
   if (!g) return CC_EINVAL;
   if (g->capturing) {
@@ -674,6 +788,9 @@ extern "C" int cc_load(cc_graph* g, const void* host_buf) {
   HIP_TRY(hipStreamSynchronize(g->stream));
   HIP_TRY(hipMemcpyAsync(g->parent, p, (size_t)g->n * 4, hipMemcpyHostToDevice, g->stream));
   HIP_TRY(hipMemcpyAsync(g->slots, h.data(), h.size() * 8, hipMemcpyHostToDevice, g->stream));
+  if (g->member) member_reset(g, 0);  // its bits were proofs about the old forest
+  g->pristine = false;
+  HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(g->stream));
   return CC_OK;
 }
@@ -685,6 +802,7 @@ extern "C" int cc_capture_begin(cc_graph* g) {
   }
   DeviceGuard dg(g->device);
   int rc = alloc_hooked(g);  // allocations cannot happen inside the capture
+  if (rc == CC_OK && g->tune.filter) rc = alloc_member(g);
   if (rc != CC_OK) return rc;
   HIP_TRY(hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal));
   g->capturing = true;
@@ -774,6 +892,8 @@ extern "C" int cc_bulk_stream(cc_graph* g, int64_t batches, const int32_t* edges
   }
   if (batches == 0) return CC_OK;
   DeviceGuard dg(g->device);
+  g->pristine = false;
+  member_touched_invalid(g);
   if (g->tune.hook == 1) return launch_stream<ByHash>(g, batches, edges, eoff, pairs, qoff, out, max_items);
   if (g->tune.hook == 2) return launch_stream<ByRank>(g, batches, edges, eoff, pairs, qoff, out, max_items);
   return launch_stream<ById>(g, batches, edges, eoff, pairs, qoff, out, max_items);

@@ -121,6 +121,22 @@ __device__ __forceinline__ int32_t find_halve(int32_t* parent, int32_t x, int32_
   return find_halve_from<R>(parent, x, ldp<R>(parent + x), cap, flags);
 }
 
+// Root of x without writing, given p = parent id of x already loaded.
+template <bool R = false>
+__device__ __forceinline__ int32_t find_read_from(const int32_t* parent, int32_t x, int32_t p, int32_t cap,
+                                                  int* flags) {
+  uint32_t steps = 0;
+  while (p != x) {
+    x = p;
+    p = ldp<R>(parent + x);
+    if (++steps > (uint32_t)cap) {
+      raise_flag(flags, kFlagCorrupt);
+      return x;
+    }
+  }
+  return x;
+}
+
 // Root of x without writing.
 template <bool R = false>
 __device__ __forceinline__ int32_t find_read(const int32_t* parent, int32_t x, int32_t cap, int* flags) {
@@ -142,20 +158,28 @@ __device__ __forceinline__ int32_t find_root(int32_t* parent, int32_t x, int32_t
   if (HALVE) return find_halve<R>(parent, x, cap, flags);
   return find_read<R>(parent, x, cap, flags);
 }
+template <bool HALVE, bool R = false>
+__device__ __forceinline__ int32_t find_root_from(int32_t* parent, int32_t x, int32_t p, int32_t cap, int* flags) {
+  if (HALVE) return find_halve_from<R>(parent, x, p, cap, flags);
+  return find_read_from<R>(parent, x, p, cap, flags);
+}
 
 // Join the trees whose (possibly stale) roots are a and b.  Returns the vertex
 // this call linked under the other tree (a former root), or -1 if the trees
-// were already one.
+// were already one; *winner (if given) gets the root it was linked under.
 template <class Ord>
 __device__ __forceinline__ int32_t link_roots(int32_t* parent, int32_t a, int32_t b, int32_t cap,
-                                              int* flags, const Ord& ord) {
+                                              int* flags, const Ord& ord, int32_t* winner = nullptr) {
   uint32_t steps = 0;
   while (a != b) {
     const bool a_wins = ord.above(a, b);
     const int32_t hi = a_wins ? b : a;  // loses: gets linked under the other
     const int32_t lo = a_wins ? a : b;
     const int32_t old = cas(parent + hi, hi, lo);
-    if (old == hi) return hi;
+    if (old == hi) {
+      if (winner) *winner = lo;
+      return hi;
+    }
     // hi stopped being a root; continue from its current parent
     const int32_t r = find_halve(parent, old, cap, flags);
     if (a_wins) b = r; else a = r;
@@ -174,7 +198,7 @@ __device__ __forceinline__ int32_t link_roots(int32_t* parent, int32_t a, int32_
 // only grows, so keys strictly increase along every parent path: no cycle.
 // A rank increment that loses a race is skipped; ranks only steer balance.
 __device__ __forceinline__ int32_t link_roots_rank(int32_t* parent, int32_t a, int32_t b, int32_t cap,
-                                                   int* flags) {
+                                                   int* flags, int32_t* winner = nullptr) {
   uint32_t steps = 0;
   while (a != b) {
     const int32_t wa = ld(parent + a), wb = ld(parent + b);
@@ -189,6 +213,7 @@ __device__ __forceinline__ int32_t link_roots_rank(int32_t* parent, int32_t a, i
       const int32_t wl = a_loses ? wa : wb, ww = a_loses ? wb : wa;
       if (cas(parent + lo, wl, hi) == wl) {
         if (ra == rb) (void)cas(parent + hi, ww, (int32_t)((uint32_t)ww + (1u << kRankShift)));
+        if (winner) *winner = hi;
         return lo;
       }
     }
@@ -213,12 +238,12 @@ struct is_ranked<ByRank> {
 
 template <class Ord>
 __device__ __forceinline__ int32_t link(int32_t* parent, int32_t a, int32_t b, int32_t cap, int* flags,
-                                        const Ord& o) {
-  return link_roots(parent, a, b, cap, flags, o);
+                                        const Ord& o, int32_t* winner = nullptr) {
+  return link_roots(parent, a, b, cap, flags, o, winner);
 }
 __device__ __forceinline__ int32_t link(int32_t* parent, int32_t a, int32_t b, int32_t cap, int* flags,
-                                        const ByRank&) {
-  return link_roots_rank(parent, a, b, cap, flags);
+                                        const ByRank&, int32_t* winner = nullptr) {
+  return link_roots_rank(parent, a, b, cap, flags, winner);
 }
 
 // Wavefront sum (64 lanes) by butterfly shuffles.

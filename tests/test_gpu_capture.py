@@ -22,7 +22,8 @@ def cc():
 
 
 @pytest.mark.parametrize("opts", [dict(), dict(update_mode=1), dict(hook=1), dict(hook=2),
-                                  dict(compress_linked=0, items=1)],
+                                  dict(compress_linked=0, items=1), dict(filter=1),
+                                  dict(filter=2, hook=2, compress_linked=0)],
                          ids=lambda o: ",".join("%s=%s" % kv for kv in sorted(o.items())) or "default")
 def test_capture_replays_match_eager(cc, opts):
     s = synth.grid_stream_cfg(W=128, H=128, batch=1 << 10, qbatch=1 << 8)

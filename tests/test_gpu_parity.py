@@ -31,6 +31,11 @@ OPTION_SETS = [
     dict(find=1, hook=1, grid_cap=16),
     dict(find=1),
     dict(find=1, hook=2),
+    dict(update_mode=0, filter=2),
+    dict(update_mode=0, hook=1, filter=1, items=8, grid_cap=5),
+    dict(update_mode=0, hook=2, filter=1, compress_linked=0),
+    dict(update_mode=0, hook=2, filter=2, block=64, items=1, query_halving=0, compress_every=2),
+    dict(update_mode=1, filter=2),
 ]
 
 

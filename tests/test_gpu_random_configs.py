@@ -26,6 +26,12 @@ def case_options(rng):
     return o
 
 
+def filter_option(seed):
+    """Drawn from its own generator so the other options of a seed stay as
+    they were before the filter existed."""
+    return int(np.random.default_rng(seed + 7919).integers(3))
+
+
 def case_stream(rng, seed):
     kind = int(rng.integers(5))
     if kind == 0:
@@ -62,6 +68,7 @@ def cc():
 def test_random_config(cc, seed):
     rng = np.random.default_rng(1000 + seed)
     opts = case_options(rng)
+    opts["filter"] = filter_option(seed)
     s = case_stream(rng, 7000 + seed)
     print("case %d: %s n=%d edges=%d batches=%d opts=%s" % (seed, s.name, s.n, len(s.edges), s.num_batches, opts),
           flush=True)
