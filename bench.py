@@ -437,13 +437,13 @@ def run_batched(args):
     # The per-graph baseline runs with its own best options: a short trial of
     # each candidate set (one step each), then the fastest is timed.
     candidates = [dict(), dict(hook=2, compress_linked=0), dict(hook=1, compress_linked=0),
-                  dict(hook=2, compress_linked=0, block=1024)]
+                  dict(hook=2, compress_linked=0, block=1024), dict(hook=2, compress_linked=0, filter=2)]
     graphs = [ccgpu.Graph(s.n) for s in streams]
     out_plain = torch.empty_like(out)
 
     def set_plain_options(o):
         for gr in graphs:
-            for k, v in {**dict(hook=0, compress_linked=1, block=256), **o}.items():
+            for k, v in {**dict(hook=0, compress_linked=1, block=256, filter=0), **o}.items():
                 gr.set_option(k, v)
 
     # views made once, as the pool's operation lists are marshalled once
@@ -626,7 +626,8 @@ def run_bigbatch(args):
         "er24": lambda: synth.er_stream(n=1 << 24, batches=1, batch=5 << 24, qbatch=1, probes=0),
     }
     schedules = {
-        "fused-rank": tuning.plain_options(1 << 24, "rmat"),
+        "fused-rank-filter": tuning.plain_options(1 << 24, "rmat"),
+        "fused-rank": dict(update_mode=0, hook=2, block=1024, compress_linked=0),
         "fused-id": dict(update_mode=0, hook=0, block=1024, compress_linked=0),
         "fused-hash": dict(update_mode=0, hook=1, block=1024, compress_linked=0),
         "contract-id": dict(update_mode=2, hook=0),
