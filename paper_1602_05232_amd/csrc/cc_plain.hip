@@ -67,6 +67,7 @@ struct cc_graph {
   int32_t* member_ctl = nullptr; // kMemberCtlWords: anchor, clear request
   int64_t member_calls = 0;      // fused updates since the filter state was last reset
   bool pristine = true;          // no update or load since creation or the last reset
+  bool touched_maybe_complete = false;  // the device's touched-complete flag may be set
   int64_t live_cap = 0;
   int64_t updates = 0;
   bool capturing = false;
@@ -77,6 +78,7 @@ struct cc_exec {
   hipGraphExec_t exec = nullptr;
   hipStream_t stream = nullptr;
   int device = 0;
+  cc_graph* graph = nullptr;  // the graph it was captured on
 };
 
 namespace {
@@ -154,14 +156,19 @@ int64_t member_words(const cc_graph* g) { return (g->n + 31) / 32; }
 void member_reset(cc_graph* g, int touched_complete) {
   const int64_t words = member_words(g);
   hipLaunchKernelGGL(k_member_ctl_reset, dim3(1), dim3(64), 0, g->stream, g->member_ctl, touched_complete);
+  g->touched_maybe_complete = touched_complete != 0;
   hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(2 * words, 256, 4096)), dim3(256), 0, g->stream,
                      (int32_t*)g->member, (int32_t)(2 * words), 0);
   g->member_calls = 0;
 }
 
 // An update that does not keep the touched bitmap complete is about to run.
+// Skipped when the flag is known to be clear already; a capture always
+// records it, since a replay may follow a reset.
 void member_touched_invalid(cc_graph* g) {
-  if (g->member) hipLaunchKernelGGL(k_member_touched_invalid, dim3(1), dim3(64), 0, g->stream, g->member_ctl);
+  if (!g->member || !(g->touched_maybe_complete || g->capturing)) return;
+  hipLaunchKernelGGL(k_member_touched_invalid, dim3(1), dim3(64), 0, g->stream, g->member_ctl);
+  g->touched_maybe_complete = false;
 }
 
 int alloc_member(cc_graph* g) {
@@ -829,6 +836,7 @@ extern "C" int cc_capture_end(cc_graph* g, cc_exec** out) {
   }
   x->stream = g->stream;
   x->device = g->device;
+  x->graph = g;
   *out = x;
   return CC_OK;
 }
@@ -837,6 +845,7 @@ extern "C" int cc_exec_launch(cc_exec* x) {
   if (!x) return CC_EINVAL;
   DeviceGuard dg(x->device);
   HIP_TRY(hipGraphLaunch(x->exec, x->stream));
+  x->graph->touched_maybe_complete = true;  // the replay may have reset the graph
   return CC_OK;
 }
 

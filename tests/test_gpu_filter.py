@@ -213,3 +213,41 @@ def test_stream_of_isolated_vertices_and_a_giant(cc):
         assert g.filter_state()[1]
         g.close()
 
+
+
+def test_replays_and_other_schedules_keep_queries_exact(cc):
+    """A replay can reset the graph behind the host's back: an update by
+    another schedule after it must still mark the touched bitmap incomplete."""
+    s = synth.rmat_stream(scale=12, size_lo=6, size_hi=11, qbatch=512)
+    half = s.num_batches // 2
+    E = dev(s.edges)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        g = cc.Graph(s.n, stream=st, filter=2)
+        g.reserve(int(np.diff(s.eoff).max()))
+        with g.capture() as cap:
+            g.reset()
+            for i in range(half):
+                g.bulk_update(E[int(s.eoff[i]):int(s.eoff[i + 1])])
+        rec = cap.recording
+        for rep in range(2):
+            rec.launch()
+            ref = oracle.UnionFind(s.n)
+            for i in range(half):
+                ref.bulk_update(s.batch(i))
+            assert g.filter_state()[1]
+            other = False  # an update by another schedule since the replay
+            for i in range(half, s.num_batches):
+                mode = 1 if i % 2 == 0 else 0
+                other = other or mode == 1
+                g.set_option("update_mode", mode)
+                ref.bulk_update(s.batch(i))
+                g.bulk_update(E[int(s.eoff[i]):int(s.eoff[i + 1])])
+                got = g.bulk_query(dev(s.query(i))).cpu().numpy()
+                np.testing.assert_array_equal(got, ref.bulk_query(s.query(i)), err_msg="replay %d minibatch %d" % (rep, i))
+                assert g.filter_state()[1] == (not other)
+                check_bits(g, ref, "replay %d minibatch %d" % (rep, i))
+            g.set_option("update_mode", 0)
+        np.testing.assert_array_equal(g.labels().cpu().numpy(), ref.labels())
+        rec.close()
+        g.close()
