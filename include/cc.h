@@ -184,8 +184,11 @@ int cc_bulk_stream(cc_graph* g, int64_t batches, const int32_t* edges, const int
 
 /* Canonical component labels: out[v] = the smallest vertex id connected to v
  * (the paper's find returns "an identifier" of the component, Section 4;
- * this fixes it to the minimum).  out is device int32[n].  Also points
- * every vertex directly at its root. */
+ * this fixes it to the minimum).  out is device int32[n].  Every vertex
+ * whose label takes a walk to its root is also pointed directly at the root;
+ * vertices that the membership filter's bitmaps settle (CC_OPT_FILTER: a
+ * member of the anchor's component, or a vertex proven alone) are not
+ * walked. */
 int cc_labels(cc_graph* g, int32_t* out);
 
 /* Number of connected components of G_t, counting isolated vertices

@@ -639,24 +639,41 @@ extern "C" int cc_bulk_query(cc_graph* g, const int32_t* pairs, int64_t q, uint8
   return CC_OK;
 }
 
+namespace {
+
+template <bool FILT>
+void launch_labels(cc_graph* g, int32_t* out) {
+  const unsigned blocks = vertex_blocks(g);
+  const int32_t n = (int32_t)g->n;
+  const int32_t* mc = g->member_ctl;
+  const uint32_t* mb = g->member;
+  if (g->tune.hook == 0) {
+    hipLaunchKernelGGL(k_labels_id<FILT>, dim3(blocks), dim3(256), 0, g->stream, g->parent, n, out, g->flags, mc, mb);
+    return;
+  }
+  hipLaunchKernelGGL(k_iota_i32, dim3(blocks), dim3(256), 0, g->stream, out, n);
+  if (g->tune.hook == 2) {
+    hipLaunchKernelGGL((k_labels_min<true, FILT>), dim3(blocks), dim3(256), 0, g->stream, g->parent, n, out, g->flags,
+                       mc, mb);
+    hipLaunchKernelGGL((k_labels_gather<true, FILT>), dim3(blocks), dim3(256), 0, g->stream, g->parent, n, out,
+                       g->flags, mc, mb);
+  } else {
+    hipLaunchKernelGGL((k_labels_min<false, FILT>), dim3(blocks), dim3(256), 0, g->stream, g->parent, n, out,
+                       g->flags, mc, mb);
+    hipLaunchKernelGGL((k_labels_gather<false, FILT>), dim3(blocks), dim3(256), 0, g->stream, g->parent, n, out,
+                       g->flags, mc, mb);
+  }
+}
+
+}  // namespace
+
+// With the membership filter's bitmaps allocated, the label passes use them
+// whatever the current options: they hold proofs either way.
 extern "C" int cc_labels(cc_graph* g, int32_t* out) {
   if (!g || !out) return CC_EINVAL;
   DeviceGuard dg(g->device);
-  const unsigned blocks = vertex_blocks(g);
-  const int32_t n = (int32_t)g->n;
-  if (g->tune.hook == 1) {
-    hipLaunchKernelGGL(k_iota_i32, dim3(blocks), dim3(256), 0, g->stream, out, n);
-    hipLaunchKernelGGL(k_labels_min<false>, dim3(blocks), dim3(256), 0, g->stream, g->parent, n, out, g->flags);
-    hipLaunchKernelGGL(k_labels_gather<false>, dim3(blocks), dim3(256), 0, g->stream, g->parent, n, out,
-                       g->flags);
-  } else if (g->tune.hook == 2) {
-    hipLaunchKernelGGL(k_iota_i32, dim3(blocks), dim3(256), 0, g->stream, out, n);
-    hipLaunchKernelGGL(k_labels_min<true>, dim3(blocks), dim3(256), 0, g->stream, g->parent, n, out, g->flags);
-    hipLaunchKernelGGL(k_labels_gather<true>, dim3(blocks), dim3(256), 0, g->stream, g->parent, n, out,
-                       g->flags);
-  } else {
-    hipLaunchKernelGGL(k_labels_id, dim3(blocks), dim3(256), 0, g->stream, g->parent, n, out, g->flags);
-  }
+  if (g->member) launch_labels<true>(g, out);
+  else launch_labels<false>(g, out);
   HIP_TRY(hipGetLastError());
   return CC_OK;
 }
