@@ -428,7 +428,11 @@ __global__ void k_query(int32_t* __restrict__ parent, const int2* __restrict__ p
         mu[k] = member_word(member, e[k].x);
         mv[k] = member_word(member, e[k].y);
       }
-      if (lone && in_range(e[k], n)) {
+    }
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      // touched words only where the membership bits did not settle the pair
+      if (lone && in_range(e[k], n) && !(filt && member_bit(mu[k], e[k].x) && member_bit(mv[k], e[k].y))) {
         tu[k] = member_word(touched, e[k].x);
         tv[k] = member_word(touched, e[k].y);
       }
