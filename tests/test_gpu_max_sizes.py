@@ -51,8 +51,11 @@ def min_labels(edges, vertices):
 
 @pytest.mark.timeout(600)
 @pytest.mark.parametrize("n,opts", [((1 << 31) - 1, dict()), ((1 << 31) - 1, dict(update_mode=2)),
-                                    (1 << 27, dict(hook=2)), (1 << 27, dict(hook=2, find=1))],
-                         ids=["2^31-1-fused", "2^31-1-contract", "2^27-rank", "2^27-rank-bulkfind"])
+                                    ((1 << 31) - 1, dict(filter=2)),
+                                    (1 << 27, dict(hook=2)), (1 << 27, dict(hook=2, find=1)),
+                                    (1 << 27, dict(hook=2, filter=2))],
+                         ids=["2^31-1-fused", "2^31-1-contract", "2^31-1-filter", "2^27-rank", "2^27-rank-bulkfind",
+                              "2^27-rank-filter"])
 def test_maximum_vertex_count(cc, n, opts):
     print("max size: n=%d opts=%s" % (n, opts), flush=True)
     edges = end_heavy_edges(n, 30000, seed=n % 1000)
@@ -67,6 +70,9 @@ def test_maximum_vertex_count(cc, n, opts):
         np.testing.assert_array_equal(g.bulk_query(torch.from_numpy(pairs).cuda()).cpu().numpy(),
                                       ref.bulk_query(pairs))
     assert g.num_components() == ref.num_components() == g.count_roots()
+    if opts.get("filter"):
+        anchor, complete, _, _ = g.filter_state()
+        assert anchor >= 0 and complete  # the bitmaps took part
     lab = g.labels()
     got = lab[torch.from_numpy(probe).cuda()].cpu().numpy()
     np.testing.assert_array_equal(got, min_labels(edges, probe))
