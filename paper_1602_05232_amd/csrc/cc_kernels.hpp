@@ -97,10 +97,10 @@ __device__ __forceinline__ int32_t settle_edge(int32_t* parent, int32_t u, int32
   const int32_t h = ru != rv ? link(parent, ru, rv, n, flags, Ord{}, &w) : -1;
   if (filt) member_join(member, u, v, bu, bv, bu || bv || ru == ra || rv == ra);
   if (touched && h >= 0) {
-    member_add(touched, h);
+    bit_set(touched, h);
     // w now has a child.  A hub root is the winning side of many links; its
     // bit is read from L2 first so that only the first few send an atomic.
-    if (!member_bit(member_word_l2(touched, w), w)) member_add(touched, w);
+    if (!bit_test(bit_word_l2(touched, w), w)) bit_set(touched, w);
   }
   return h;
 }
@@ -198,8 +198,8 @@ __global__ void k_update_fused(int32_t* __restrict__ parent, const int2* __restr
     for (int k = 0; k < ITEMS; ++k) {
       mu[k] = mv[k] = 0u;
       if (filt && in_range(e[k], n)) {
-        mu[k] = member_word(member, e[k].x);
-        mv[k] = member_word(member, e[k].y);
+        mu[k] = bit_word(member, e[k].x);
+        mv[k] = bit_word(member, e[k].y);
       }
     }
     if (FILT) {
@@ -212,7 +212,7 @@ __global__ void k_update_fused(int32_t* __restrict__ parent, const int2* __restr
           continue;
         }
         const int32_t u = e[k].x, v = e[k].y;
-        const bool bu = filt && member_bit(mu[k], u), bv = filt && member_bit(mv[k], v);
+        const bool bu = filt && bit_test(mu[k], u), bv = filt && bit_test(mv[k], v);
         if (u == v || (bu && bv)) {
           e[k] = make_int2(0, 0);
           continue;
@@ -425,16 +425,16 @@ __global__ void k_query(int32_t* __restrict__ parent, const int2* __restrict__ p
     for (int k = 0; k < ITEMS; ++k) {
       mu[k] = mv[k] = tu[k] = tv[k] = 0u;
       if ((filt || lone) && in_range(e[k], n)) {
-        mu[k] = member_word(member, e[k].x);
-        mv[k] = member_word(member, e[k].y);
+        mu[k] = bit_word(member, e[k].x);
+        mv[k] = bit_word(member, e[k].y);
       }
     }
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
       // touched words only where the membership bits did not settle the pair
-      if (lone && in_range(e[k], n) && !(filt && member_bit(mu[k], e[k].x) && member_bit(mv[k], e[k].y))) {
-        tu[k] = member_word(touched, e[k].x);
-        tv[k] = member_word(touched, e[k].y);
+      if (lone && in_range(e[k], n) && !(filt && bit_test(mu[k], e[k].x) && bit_test(mv[k], e[k].y))) {
+        tu[k] = bit_word(touched, e[k].x);
+        tv[k] = bit_word(touched, e[k].y);
       }
     }
     int32_t pu[ITEMS], pv[ITEMS];
@@ -449,12 +449,12 @@ __global__ void k_query(int32_t* __restrict__ parent, const int2* __restrict__ p
         continue;
       }
       const int32_t u = e[k].x, v = e[k].y;
-      if (u == v || (filt && member_bit(mu[k], u) && member_bit(mv[k], v))) {
+      if (u == v || (filt && bit_test(mu[k], u) && bit_test(mv[k], v))) {
         a[k] = 1;
         continue;
       }
       // a vertex in neither bitmap has never had an edge: alone, so not connected to the other
-      if (lone && ((!member_bit(mu[k], u) && !member_bit(tu[k], u)) || (!member_bit(mv[k], v) && !member_bit(tv[k], v))))
+      if (lone && ((!bit_test(mu[k], u) && !bit_test(tu[k], u)) || (!bit_test(mv[k], v) && !bit_test(tv[k], v))))
         continue;
       open |= 1u << k;
       pu[k] = ldp<R>(parent + u);
@@ -468,11 +468,11 @@ __global__ void k_query(int32_t* __restrict__ parent, const int2* __restrict__ p
       const int32_t rv = find_root_from<HALVE, R>(parent, v, pv[k], n, flags);
       a[k] = ru == rv;
       if (filt) {
-        const bool bu = member_bit(mu[k], u), bv = member_bit(mv[k], v);
+        const bool bu = bit_test(mu[k], u), bv = bit_test(mv[k], v);
         bool iu = bu || ru == ra, iv = bv || rv == ra;
         if (a[k]) iu = iv = iu || iv;
-        if (iu && !bu) member_add(member, u);
-        if (iv && !bv) member_add(member, v);
+        if (iu && !bu) bit_set(member, u);
+        if (iv && !bv) bit_set(member, v);
       }
     }
 #pragma unroll

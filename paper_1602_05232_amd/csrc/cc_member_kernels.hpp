@@ -25,7 +25,8 @@
 // The anchor is chosen by k_anchor_pick, on a sparse schedule of update
 // calls: it samples endpoints of the minibatch, finds their roots and takes
 // the root shared by most of them.  A change of anchor to another component
-// clears the bitmap (k_member_clear) before the update that follows.
+// empties the membership bitmap (k_member_clear, which first moves its bits
+// into the touched bitmap below) before the update that follows.
 //
 // A second bitmap of the same size, `touched`, gets the bits of both ends of
 // every link the filtered update makes: the root linked under another tree,
@@ -48,19 +49,20 @@ constexpr int kPickThreads = 512;   // sampled edges per pick (two endpoints eac
 constexpr int kPickSlots = 2048;    // LDS hash table of sampled roots
 constexpr int kMemberCtlWords = 16;  // [0] anchor (-1: none), [1] clear request, [2] touched bitmap complete
 
-// The bitmap word holding v's bit, and v's bit in it.  A word read before
-// another thread set a bit only misses that bit (the item takes the full
-// path), so plain loads that may hit a stale cached copy are fine.
-__device__ __forceinline__ uint32_t member_word(const uint32_t* bits, int32_t v) {
+// Bitmap helpers (both bitmaps): the word holding v's bit, and v's bit in
+// it.  A word read before another thread set a bit only misses that bit (the
+// item takes the full path), so plain loads that may hit a stale cached copy
+// are fine.
+__device__ __forceinline__ uint32_t bit_word(const uint32_t* bits, int32_t v) {
   return __hip_atomic_load(const_cast<uint32_t*>(bits + (v >> 5)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
-__device__ __forceinline__ bool member_bit(uint32_t word, int32_t v) { return (word >> (v & 31)) & 1u; }
+__device__ __forceinline__ bool bit_test(uint32_t word, int32_t v) { return (word >> (v & 31)) & 1u; }
 // The same word read at device scope (from L2, where the atomics land).
-__device__ __forceinline__ uint32_t member_word_l2(const uint32_t* bits, int32_t v) {
+__device__ __forceinline__ uint32_t bit_word_l2(const uint32_t* bits, int32_t v) {
   return __hip_atomic_load(const_cast<uint32_t*>(bits + (v >> 5)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ void member_add(uint32_t* bits, int32_t v) {
+__device__ __forceinline__ void bit_set(uint32_t* bits, int32_t v) {
   __hip_atomic_fetch_or(bits + (v >> 5), 1u << (v & 31), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -75,11 +77,12 @@ __device__ __forceinline__ int32_t anchor_root(const int32_t* parent, const int3
 
 // After u and v are known to be in one tree (joined by this thread, or found
 // joined): if either is known to be connected to the anchor, so is the other.
-// in_u / in_v: bit already set, or the vertex's root is the anchor's root.
+// bu, bv: their membership bits as read earlier; in: either bit set, or
+// either end's root (or parent) is the anchor's root.
 __device__ __forceinline__ void member_join(uint32_t* bits, int32_t u, int32_t v, bool bu, bool bv, bool in) {
   if (!in) return;
-  if (!bu) member_add(bits, u);
-  if (!bv) member_add(bits, v);
+  if (!bu) bit_set(bits, u);
+  if (!bv) bit_set(bits, v);
 }
 
 __device__ __forceinline__ void pick_insert(int32_t* key, int32_t* cnt, int32_t r) {

@@ -17,9 +17,9 @@ namespace {  // kernels get internal linkage in every translation unit
 // of root ra), 2 = alone, 0 = unknown.
 __device__ __forceinline__ int label_class(const uint32_t* member, const uint32_t* touched, int32_t v, int32_t ra,
                                            bool lone) {
-  const bool m = ra >= 0 && member_bit(member_word(member, v), v);
+  const bool m = ra >= 0 && bit_test(bit_word(member, v), v);
   if (m) return 1;
-  if (lone && !member_bit(member_word(member, v), v) && !member_bit(member_word(touched, v), v)) return 2;
+  if (lone && !bit_test(bit_word(member, v), v) && !bit_test(bit_word(touched, v), v)) return 2;
   return 0;
 }
 
