@@ -25,7 +25,7 @@
 // The anchor is chosen by k_anchor_pick, on a sparse schedule of update
 // calls: it samples endpoints of the minibatch, finds their roots and takes
 // the root shared by most of them.  A change of anchor to another component
-// empties the membership bitmap (k_member_clear, which first moves its bits
+// refills the membership bitmap (k_member_reseed, which first moves its bits
 // into the touched bitmap below) before the update that follows.
 //
 // A second bitmap of the same size, `touched`, gets the bits of both ends of
@@ -102,7 +102,7 @@ __device__ __forceinline__ void pick_insert(int32_t* key, int32_t* cnt, int32_t 
 // endpoints (read-only), and counts the sampled endpoints per root.  The
 // most frequent root becomes the anchor when it holds at least 1/8 of the
 // sampled endpoints, at least 16 of them, and more than twice as many as the
-// current anchor's component; ctl[1] then asks k_member_clear to clear the
+// current anchor's component; ctl[1] then asks k_member_reseed to refill the
 // bitmap, since its bits were proofs of connection to the old anchor.
 template <bool R>
 __global__ __launch_bounds__(kPickThreads) void k_anchor_pick(const int32_t* __restrict__ parent,
@@ -169,16 +169,31 @@ __global__ __launch_bounds__(kPickThreads) void k_anchor_pick(const int32_t* __r
 // When the last pick changed the anchor (ctl[1] != 0): moves every
 // membership bit into the touched bitmap (a member has had an edge, or is
 // about to get one in the update that follows its pick; a touched bit that
-// is set without need only costs a find) and clears the membership bitmap.
+// is set without need only costs a find) and refills the membership bitmap
+// with what one coalesced pass over `parent` proves: the new anchor's root
+// and every vertex whose parent it is.  Under union by rank most of a
+// component hangs directly under its root, so the update that follows starts
+// with most of the component known instead of an empty bitmap.  A wavefront
+// covers 64 consecutive vertices, two bitmap words, which its ballot fills.
 // bits: `words` membership words followed by `words` touched words.
-__global__ void k_member_clear(const int32_t* __restrict__ ctl, uint32_t* __restrict__ bits, int64_t words) {
+template <bool R>
+__global__ void k_member_reseed(const int32_t* __restrict__ parent, int32_t n, const int32_t* __restrict__ ctl,
+                                uint32_t* __restrict__ bits, int64_t words, int* __restrict__ flags) {
   if (__hip_atomic_load(const_cast<int32_t*>(ctl + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) return;
+  const int32_t ra = anchor_root<R>(parent, ctl, n, flags);
   uint32_t* touched = bits + words;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t w = bits[i];
-    if (w) {
-      touched[i] |= w;
-      bits[i] = 0u;
+  const int lane = threadIdx.x & 63;
+  // blockDim.x is a multiple of 64 and every wavefront starts at a multiple of 64
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i - lane < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const bool in = i < n && ra >= 0 && (i == ra || pid<R>(parent[i]) == ra);
+    const unsigned long long mask = __ballot(in);
+    if (lane == 0 || lane == 32) {
+      const int64_t w = i >> 5;  // the word of this lane's 32 vertices
+      if (w < words) {
+        const uint32_t old = bits[w];
+        if (old) touched[w] |= old;
+        bits[w] = lane == 0 ? (uint32_t)mask : (uint32_t)(mask >> 32);
+      }
     }
   }
 }

@@ -194,9 +194,8 @@ void member_pick(cc_graph* g, const int2* e, int64_t m) {
   if ((c & (c - 1)) != 0 && c % 64 != 0) return;
   hipLaunchKernelGGL(k_anchor_pick<R>, dim3(1), dim3(kPickThreads), 0, g->stream, g->parent, e, m,
                      (int32_t)g->n, g->member_ctl, g->flags);
-  const int64_t words = member_words(g);
-  hipLaunchKernelGGL(k_member_clear, dim3(blocks_for(words, 256, 256)), dim3(256), 0, g->stream, g->member_ctl,
-                     g->member, words);
+  hipLaunchKernelGGL(k_member_reseed<R>, dim3(blocks_for(g->n, 256, 1024)), dim3(256), 0, g->stream, g->parent,
+                     (int32_t)g->n, g->member_ctl, g->member, member_words(g), g->flags);
 }
 
 int launch_init(cc_graph* g) {
