@@ -118,7 +118,11 @@ enum cc_option {
    * (and a clearing launch) before update calls 0, 1, 2, 4, 8, ... and every
    * 64th call after a reset or load.  The split and contracting schedules,
    * Bulk-Find and cc_bulk_stream neither use nor update it.  Default 0. */
-  CC_OPT_FILTER = 12
+  CC_OPT_FILTER = 12,
+  /* Pairs per thread of Bulk-Query: 1, 2, 4 or 8, or 0 = as CC_OPT_ITEMS
+   * (default).  Queries gain from more pairs in flight per thread where the
+   * filtered update wants one edge per thread. */
+  CC_OPT_QUERY_ITEMS = 13
 };
 
 /* Create a graph on vertices [0, n), 1 <= n <= 2^31 - 1, every vertex its own

@@ -55,6 +55,7 @@ struct Tuning {
   int find = 0;                  // CC_OPT_FIND
   int one_launch = 0;            // CC_OPT_ONE_LAUNCH (pools)
   int filter = 0;                // CC_OPT_FILTER
+  int query_items = 0;           // CC_OPT_QUERY_ITEMS (0 = as CC_OPT_ITEMS)
 };
 
 inline bool set_tuning(Tuning* t, int key, int64_t v) {
@@ -107,6 +108,10 @@ inline bool set_tuning(Tuning* t, int key, int64_t v) {
       if (v < 0 || v > 2) return false;
       t->filter = (int)v;
       return true;
+    case CC_OPT_QUERY_ITEMS:
+      if (v != 0 && v != 1 && v != 2 && v != 4 && v != 8) return false;
+      t->query_items = (int)v;
+      return true;
     default:
       return false;
   }
@@ -126,6 +131,7 @@ inline bool get_tuning(const Tuning* t, int key, int64_t* v) {
     case CC_OPT_FIND: *v = t->find; return true;
     case CC_OPT_ONE_LAUNCH: *v = t->one_launch; return true;
     case CC_OPT_FILTER: *v = t->filter; return true;
+    case CC_OPT_QUERY_ITEMS: *v = t->query_items; return true;
     default: return false;
   }
 }

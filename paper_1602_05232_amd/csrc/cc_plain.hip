@@ -287,7 +287,8 @@ void launch_query_t(cc_graph* g, const int2* p, int64_t q, uint8_t* out) {
 
 template <bool HALVE, bool R, bool FILT>
 void launch_query_f(cc_graph* g, const int2* p, int64_t q, uint8_t* out) {
-  switch (cc::pick_items(g->tune.items, q, g->tune.block)) {
+  const int items = g->tune.query_items ? g->tune.query_items : g->tune.items;
+  switch (cc::pick_items(items, q, g->tune.block)) {
     case 1: launch_query_t<1, HALVE, R, FILT>(g, p, q, out); break;
     case 2: launch_query_t<2, HALVE, R, FILT>(g, p, q, out); break;
     case 8: launch_query_t<8, HALVE, R, FILT>(g, p, q, out); break;

@@ -36,6 +36,8 @@ OPTION_SETS = [
     dict(update_mode=0, hook=2, filter=1, compress_linked=0),
     dict(update_mode=0, hook=2, filter=2, block=64, items=1, query_halving=0, compress_every=2),
     dict(update_mode=1, filter=2),
+    dict(update_mode=0, hook=2, filter=2, items=1, query_items=4, block=512, grid_cap=768, compress_linked=0),
+    dict(update_mode=0, query_items=8, block=128),
 ]
 
 

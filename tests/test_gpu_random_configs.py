@@ -32,6 +32,11 @@ def filter_option(seed):
     return int(np.random.default_rng(seed + 7919).integers(3))
 
 
+def query_items_option(seed):
+    """Likewise for the query's own items per thread."""
+    return int(np.random.default_rng(seed + 104729).choice([0, 0, 1, 2, 4, 8]))
+
+
 def case_stream(rng, seed):
     kind = int(rng.integers(5))
     if kind == 0:
@@ -69,6 +74,7 @@ def test_random_config(cc, seed):
     rng = np.random.default_rng(1000 + seed)
     opts = case_options(rng)
     opts["filter"] = filter_option(seed)
+    opts["query_items"] = query_items_option(seed)
     s = case_stream(rng, 7000 + seed)
     print("case %d: %s n=%d edges=%d batches=%d opts=%s" % (seed, s.name, s.n, len(s.edges), s.num_batches, opts),
           flush=True)
