@@ -443,6 +443,7 @@ def run_batched(args):
 
     def set_plain_options(o):
         for gr in graphs:
+            gr.reset()  # the linking order may change only on a fresh forest
             for k, v in {**dict(hook=0, compress_linked=1, block=256, filter=0), **o}.items():
                 gr.set_option(k, v)
 

@@ -81,7 +81,10 @@ enum cc_option {
                                 the root (default); 1 = by a hashed priority (fmix32);
                                 2 = union by rank (the balanced linking of Section 4
                                 with ranks in place of sizes; a root's rank sits in
-                                bits 27-31 of its word, so n <= 2^27) */
+                                bits 27-31 of its word, so n <= 2^27).  Can change
+                                only while the graph has had no update since its
+                                creation or the last cc_reset (CC_EINVAL otherwise);
+                                a load keeps the order it was checked against. */
   CC_OPT_GRID_CAP = 7,       /* upper bound on blocks per launch (grid-stride beyond it);
                                 default 4096 */
   /* Fused schedule: 1 = record the roots each update links and afterwards

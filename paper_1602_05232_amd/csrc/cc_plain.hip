@@ -64,7 +64,7 @@ struct cc_graph {
   bool bf_ready = false;
   int64_t bf_seg0_entries = 0;   // allocated level-0 entries
   uint32_t* member = nullptr;    // membership bitmap of the filter, ceil(n / 32) words
-  int32_t* member_ctl = nullptr; // kMemberCtlWords: anchor, clear request
+  int32_t* member_ctl = nullptr; // kMemberCtlWords: anchor, clear request, touched-complete flag
   int64_t member_calls = 0;      // fused updates since the filter state was last reset
   bool pristine = true;          // no update or load since creation or the last reset
   bool touched_maybe_complete = false;  // the device's touched-complete flag may be set
@@ -494,6 +494,13 @@ extern "C" int cc_set_option(cc_graph* g, int key, int64_t value) {
     cc_set_error("cc_set_option: union by rank needs n <= 2^%d", kRankShift);
     return CC_EINVAL;
   }
+  // The forest's words and every label pass assume one linking order for
+  // all links so far (rank bits sit in root words under union by rank).
+  if (key == CC_OPT_HOOK && value != g->tune.hook && !g->pristine) {
+    cc_set_error("cc_set_option: the linking order can change only before the first update after creation or "
+                 "cc_reset");
+    return CC_EINVAL;
+  }
   if (!cc::set_tuning(&g->tune, key, value)) {
     cc_set_error("cc_set_option: key %d value %lld rejected", key, (long long)value);
     return CC_EINVAL;
@@ -542,12 +549,13 @@ extern "C" int cc_bulk_update(cc_graph* g, const int32_t* edges, int64_t m) {
   if (m == 0) return CC_OK;
   DeviceGuard dg(g->device);
   const int2* e = reinterpret_cast<const int2*>(edges);
-  const bool was_pristine = g->pristine;
-  g->pristine = false;
   if (g->tune.find == 1) {
     member_touched_invalid(g);
     int rc = launch_bulk_find<0>(g, e, m, nullptr);
-    if (rc == CC_OK) g->updates++;
+    if (rc == CC_OK) {
+      g->updates++;
+      g->pristine = false;
+    }
     return rc;
   }
   const bool hashed = g->tune.hook == 1, ranked = g->tune.hook == 2;
@@ -596,9 +604,7 @@ extern "C" int cc_bulk_update(cc_graph* g, const int32_t* edges, int64_t m) {
         cc_set_error("cc_bulk_update: call cc_reserve before capturing");
         return CC_EINVAL;
       }
-      g->pristine = was_pristine;  // this update is the filter's first
-      int rc = alloc_member(g);
-      g->pristine = false;
+      int rc = alloc_member(g);  // still pristine if this is the graph's first update
       if (rc != CC_OK) return rc;
     }
     if (ranked) launch_fused_o<ByRank>(g, e, m);
@@ -606,6 +612,7 @@ extern "C" int cc_bulk_update(cc_graph* g, const int32_t* edges, int64_t m) {
     else launch_fused_o<ById>(g, e, m);
   }
   g->updates++;
+  g->pristine = false;
   if (g->tune.compress_every > 0 && g->updates % g->tune.compress_every == 0) {
     if (ranked)
       hipLaunchKernelGGL(k_compress_all<true>, dim3(vertex_blocks(g)), dim3(256), 0, g->stream, g->parent,

@@ -228,6 +228,41 @@ def test_argument_errors(cc):
     g.close()
 
 
+def test_linking_order_is_fixed_until_reset(cc):
+    """Rank bits live in root words and the label passes assume one order, so
+    the order may change only on a fresh forest; a rejected update leaves the
+    graph fresh."""
+    s = synth.rmat_stream(scale=12, size_lo=6, size_hi=11, qbatch=256)
+    g = cc.Graph(s.n, hook=2, update_mode=1)
+    with pytest.raises(cc.CCError):
+        g.bulk_update(dev(s.batch(0)))  # rank needs the fused schedule: nothing runs
+    g.set_option("hook", 1)  # still fresh
+    g.set_option("update_mode", 0)
+    ref = oracle.UnionFind(s.n)
+    ref.bulk_update(s.batch(0))
+    g.bulk_update(dev(s.batch(0)))
+    for h in (0, 2):
+        with pytest.raises(cc.CCError) as ei:
+            g.set_option("hook", h)
+        assert ei.value.code == cc.cc.CC_EINVAL
+    g.set_option("hook", 1)  # the same order is not a change
+    np.testing.assert_array_equal(g.labels().cpu().numpy(), ref.labels())
+    img = g.save()
+    g.reset()
+    g.set_option("hook", 2)
+    ref = oracle.UnionFind(s.n)
+    for i in range(s.num_batches):
+        ref.bulk_update(s.batch(i))
+        g.bulk_update(dev(s.batch(i)))
+    np.testing.assert_array_equal(g.labels().cpu().numpy(), ref.labels())
+    g.reset()
+    g.set_option("hook", 1)
+    g.load(img)  # checked against the hashed order, then fixed
+    with pytest.raises(cc.CCError):
+        g.set_option("hook", 0)
+    g.close()
+
+
 @pytest.mark.parametrize("hook", [0, 1, 2])
 def test_save_load_resume(cc, hook):
     s = synth.rmat_stream(scale=14, size_lo=8, size_hi=13, qbatch=256)
