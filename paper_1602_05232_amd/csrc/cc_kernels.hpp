@@ -397,13 +397,12 @@ __global__ void k_compress_hooked(int32_t* __restrict__ parent, const int32_t* _
   }
 }
 
-// Same phases as the fused update: membership and touched words (FILT), then
-// the parents of the pairs still open, then the finds.  With FILT, a pair
-// whose endpoints are both in the membership bitmap answers 1 without a
-// find; while the touched bitmap is complete, a pair with an endpoint in
-// neither bitmap answers 0 without a find; and an endpoint whose find meets
-// the anchor's root (or that is found joined to a member) is added to the
-// membership bitmap.
+// Phases: touched and membership words (FILT), then the parents of the
+// pairs still open, then the finds.  With FILT, while the touched bitmap is
+// complete a pair with an end outside it answers 0 without a find; a pair
+// whose ends are both in the membership bitmap answers 1 without a find; and
+// an end whose find meets the anchor's root (or that is found joined to a
+// member) is added to the membership bitmap.
 template <int ITEMS, bool HALVE, bool R, bool FILT>
 __global__ void k_query(int32_t* __restrict__ parent, const int2* __restrict__ pairs, int64_t q, int32_t n,
                         uint8_t* __restrict__ out, int* __restrict__ flags, const int32_t* __restrict__ member_ctl,
@@ -420,23 +419,28 @@ __global__ void k_query(int32_t* __restrict__ parent, const int2* __restrict__ p
       const int64_t i = t0 + (int64_t)k * blockDim.x + threadIdx.x;
       e[k] = i < q ? pairs[i] : make_int2(0, 0);
     }
+    // While the touched bitmap is complete it holds every vertex that has
+    // had an edge, members included (a member is connected to the anchor,
+    // and an anchor that is still alone when picked is linked by the update
+    // that follows the pick).  So the touched words go first: a clear bit
+    // settles the pair as 0, and membership words are read only for pairs
+    // whose ends have both had edges.
     uint32_t mu[ITEMS], mv[ITEMS], tu[ITEMS], tv[ITEMS];
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
-      mu[k] = mv[k] = tu[k] = tv[k] = 0u;
-      if ((filt || lone) && in_range(e[k], n)) {
-        mu[k] = bit_word(member, e[k].x);
-        mv[k] = bit_word(member, e[k].y);
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-      // touched words only where the membership bits did not settle the pair
-      if (lone && in_range(e[k], n) && !(filt && bit_test(mu[k], e[k].x) && bit_test(mv[k], e[k].y))) {
+      mu[k] = mv[k] = 0u;
+      tu[k] = tv[k] = ~0u;
+      if (lone && in_range(e[k], n)) {
         tu[k] = bit_word(touched, e[k].x);
         tv[k] = bit_word(touched, e[k].y);
       }
     }
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k)
+      if (filt && in_range(e[k], n) && bit_test(tu[k], e[k].x) && bit_test(tv[k], e[k].y)) {
+        mu[k] = bit_word(member, e[k].x);
+        mv[k] = bit_word(member, e[k].y);
+      }
     int32_t pu[ITEMS], pv[ITEMS];
     uint8_t a[ITEMS];
     unsigned open = 0;
@@ -449,13 +453,16 @@ __global__ void k_query(int32_t* __restrict__ parent, const int2* __restrict__ p
         continue;
       }
       const int32_t u = e[k].x, v = e[k].y;
-      if (u == v || (filt && bit_test(mu[k], u) && bit_test(mv[k], v))) {
+      if (u == v) {
         a[k] = 1;
         continue;
       }
-      // a vertex in neither bitmap has never had an edge: alone, so not connected to the other
-      if (lone && ((!bit_test(mu[k], u) && !bit_test(tu[k], u)) || (!bit_test(mv[k], v) && !bit_test(tv[k], v))))
+      // an end that has never had an edge is alone, so not connected to the other
+      if (!bit_test(tu[k], u) || !bit_test(tv[k], v)) continue;
+      if (filt && bit_test(mu[k], u) && bit_test(mv[k], v)) {
+        a[k] = 1;
         continue;
+      }
       open |= 1u << k;
       pu[k] = ldp<R>(parent + u);
       pv[k] = ldp<R>(parent + v);

@@ -33,7 +33,8 @@ def members(bits, n):
 
 def check_bits(g, ref, where):
     """Every member is connected to the anchor; while the touched bitmap is
-    complete, every vertex in neither bitmap is alone."""
+    complete, every vertex that is not alone has its touched bit (members
+    included: queries read the touched words alone to prove a vertex alone)."""
     anchor, complete, bits, touched = g.filter_state()
     got = members(bits, g.n)
     lab = ref.labels()
@@ -44,11 +45,11 @@ def check_bits(g, ref, where):
         assert len(bad) == 0, "%s: %d member bits outside the anchor's component, e.g. %s" % (where, len(bad), bad[:8])
     if complete:
         known = np.zeros(g.n, bool)
-        known[got] = True
         known[members(touched, g.n)] = True
         size = np.bincount(lab, minlength=g.n)[lab]
         bad = np.flatnonzero(~known & (size > 1))
-        assert len(bad) == 0, "%s: %d vertices with edges in neither bitmap, e.g. %s" % (where, len(bad), bad[:8])
+        assert len(bad) == 0, "%s: %d vertices with edges outside the touched bitmap, e.g. %s" % (
+            where, len(bad), bad[:8])
     return anchor, got
 
 
