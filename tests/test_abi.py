@@ -51,3 +51,15 @@ def test_strerror_and_invalid_args_without_device(libcc):
     assert L.cc_num_vertices(None) == 0
     assert not L.cc_create(0)
     assert b"outside" in L.cc_last_error()
+
+
+def test_option_constants_match_the_header():
+    """The binding's option numbers and names are those of enum cc_option."""
+    from paper_1602_05232_amd import cc
+    src = open(os.path.join(ROOT, "include", "cc.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    enum = dict((k, int(v)) for k, v in re.findall(r"\b(CC_OPT_[A-Z_]+)\s*=\s*(\d+)", src))
+    assert len(enum) >= 13
+    for name, value in enum.items():
+        assert getattr(cc, name[3:]) == value, name  # CC_OPT_X -> cc.OPT_X
+    assert set(cc._OPT_NAMES.values()) == set(enum.values())
