@@ -63,3 +63,27 @@ def test_option_constants_match_the_header():
     for name, value in enum.items():
         assert getattr(cc, name[3:]) == value, name  # CC_OPT_X -> cc.OPT_X
     assert set(cc._OPT_NAMES.values()) == set(enum.values())
+
+
+def test_tuned_options_are_known_and_in_range():
+    """Every stored option set names options of the binding with values the
+    library accepts (ranges of include/cc.h), so a lookup never fails at
+    graph creation."""
+    import json
+    from paper_1602_05232_amd import cc, tuning
+    allowed = {"update_mode": {0, 1, 2}, "block": set(range(64, 1025, 64)), "items": {0, 1, 2, 4, 8},
+               "query_items": {0, 1, 2, 4, 8}, "query_halving": {0, 1}, "hook": {0, 1, 2},
+               "compress_linked": {0, 1}, "filter": {0, 1, 2}, "find": {0, 1}, "one_launch": {0, 1}}
+    tab = json.load(open(tuning.CACHE))
+    assert "plain/rmat/24" in tab
+    for key, opts in list(tab.items()) + [("defaults", tuning.DEFAULTS)]:
+        for k, v in opts.items():
+            assert k in cc._OPT_NAMES, (key, k)
+            if k in allowed:
+                assert v in allowed[k], (key, k, v)
+            elif k == "grid_cap":
+                assert 1 <= v <= 1 << 20
+            elif k == "compress_every":
+                assert v >= 0
+        if key.startswith("plain/") and opts.get("hook") == 2:
+            assert opts.get("update_mode", 0) == 0, key  # rank linking takes the fused schedule only
