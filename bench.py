@@ -192,13 +192,15 @@ def run_rmat(args):
     stream = torch.cuda.current_stream()
     # ev[2i] .. ev[2i+1]: update i; ev[2i+1] .. ev[2i+2]: query i.  Timing-only
     # events: a default event's cache writeback per record costs ~3.6 us of
-    # GPU time, 0.8 ms per step at three records per minibatch.
-    ev = [roofline.TimingEvent() for _ in range(2 * nb + 1)]
+    # GPU time, 0.8 ms per step at three records per minibatch.  Each timed
+    # step records into its own set, read after the timed region, so that
+    # reading 2 * nb intervals on the host is not counted as step time.
+    ev_sets = [[roofline.TimingEvent() for _ in range(2 * nb + 1)] for _ in range(max(1, args.steps))]
     Es = [E[eoff[i]:eoff[i + 1]] for i in range(nb)]
     Qs = [Q[qoff[i]:qoff[i + 1]] for i in range(nb)]
     Os = [out[qoff[i]:qoff[i + 1]] for i in range(nb)]
 
-    def step():
+    def step(ev):
         g.reset()
         for i in range(nb):
             ev[2 * i].record(stream)
@@ -210,21 +212,24 @@ def run_rmat(args):
         return g.num_components()  # waits for the stream
 
     for k in range(args.warmup):
-        c = step()
+        c = step(ev_sets[0])
         log("warmup step %d done: components=%d" % (k, c))
     torch.cuda.synchronize()
-    upd_t, qry_t, upd_lat = [], [], []
     t0 = time.perf_counter()
     for k in range(args.steps):
-        c = step()
+        c = step(ev_sets[k])
+        log("step %d done: components=%d" % (k, c))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    upd_t, qry_t, upd_lat = [], [], []
+    for k in range(args.steps):
+        ev = ev_sets[k]
         tu = [ev[2 * i].elapsed_time(ev[2 * i + 1]) / 1e3 for i in range(nb)]
         tq = [ev[2 * i + 1].elapsed_time(ev[2 * i + 2]) / 1e3 for i in range(nb)]
         upd_t.append(sum(tu))
         qry_t.append(sum(tq))
         upd_lat.extend(x * 1e3 for x in tu)
-        log("step %d done: components=%d update %.4fs query %.4fs" % (k, c, upd_t[-1], qry_t[-1]))
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+        log("step %d: update %.4fs query %.4fs" % (k, upd_t[-1], qry_t[-1]))
     rc = g.sync()
     if rc != 0:
         raise SystemExit("device reported status %d" % rc)
