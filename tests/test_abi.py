@@ -51,6 +51,11 @@ def test_strerror_and_invalid_args_without_device(libcc):
     assert L.cc_num_vertices(None) == 0
     assert not L.cc_create(0)
     assert b"outside" in L.cc_last_error()
+    import ctypes
+    a, c = ctypes.c_int32(), ctypes.c_int32()
+    assert L.cc_filter_state(None, ctypes.byref(a), ctypes.byref(c), None) == cc.CC_EINVAL
+    assert L.cc_set_option(None, cc.OPT_FILTER, 1) == cc.CC_EINVAL
+    assert L.cc_get_option(None, cc.OPT_QUERY_ITEMS, None) == cc.CC_EINVAL
 
 
 def test_option_constants_match_the_header():
