@@ -183,16 +183,40 @@ __global__ void k_member_reseed(const int32_t* __restrict__ parent, int32_t n, c
   const int32_t ra = anchor_root<R>(parent, ctl, n, flags);
   uint32_t* touched = bits + words;
   const int lane = threadIdx.x & 63;
-  // blockDim.x is a multiple of 64 and every wavefront starts at a multiple of 64
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i - lane < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const bool in = i < n && ra >= 0 && (i == ra || pid<R>(parent[i]) == ra);
-    const unsigned long long mask = __ballot(in);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  constexpr int G = 4;  // 64-vertex groups per wavefront per pass, their loads in flight together
+  // blockDim.x is a multiple of 64 and every wavefront starts at a multiple of
+  // 64, so `i - lane` (the group's first vertex) is the same in all its lanes
+  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i0 - lane < n; i0 += G * stride) {
+    int32_t p[G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      const int64_t i = i0 + k * stride;
+      p[k] = i < n ? pid<R>(parent[i]) : -1;
+    }
+    // the two word-writing lanes of each group: its new words, then all the
+    // old words read together, then the writes
+    uint32_t fresh[G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      const int64_t i = i0 + k * stride;
+      const bool in = i < n && ra >= 0 && (i == ra || p[k] == ra);
+      const unsigned long long mask = __ballot(in);  // groups past n give 0 and are not written
+      fresh[k] = lane == 0 ? (uint32_t)mask : (uint32_t)(mask >> 32);
+    }
     if (lane == 0 || lane == 32) {
-      const int64_t w = i >> 5;  // the word of this lane's 32 vertices
-      if (w < words) {
-        const uint32_t old = bits[w];
-        if (old) touched[w] |= old;
-        bits[w] = lane == 0 ? (uint32_t)mask : (uint32_t)(mask >> 32);
+      uint32_t old[G];
+#pragma unroll
+      for (int k = 0; k < G; ++k) {
+        const int64_t w = (i0 + k * stride) >> 5;  // the word of this lane's 32 vertices
+        old[k] = w < words ? bits[w] : 0u;
+      }
+#pragma unroll
+      for (int k = 0; k < G; ++k) {
+        const int64_t w = (i0 + k * stride) >> 5;
+        if (w >= words) continue;
+        if (old[k]) touched[w] |= old[k];
+        bits[w] = fresh[k];
       }
     }
   }
