@@ -109,22 +109,28 @@ enum cc_option {
    * launch, separated by device-wide barriers, instead of one launch per
    * round; no linked-root compression in that form.  Default 0. */
   CC_OPT_ONE_LAUNCH = 11,
-  /* Membership filter of the largest component: a bitmap (n / 8 bytes of
-   * device memory) of vertices proven connected to an anchor vertex, chosen
-   * as the root most sampled minibatch endpoints lead to.  1 = under the
-   * fused schedule an edge whose endpoints are both in it is dropped without
-   * a find (it could only join a component with itself); 2 = that, and
-   * Bulk-Query also answers such a pair 1 without a find (and adds the
-   * endpoints its finds prove connected).  Bits are set only from proofs
-   * (a find that meets the anchor's root, or an edge joined to a member), so
-   * results are unchanged.  Choosing the anchor costs one single-block launch
-   * (and a clearing launch) before update calls 0, 1, 2, 4, 8, ... and every
-   * 64th call after a reset or load.  The split and contracting schedules,
-   * Bulk-Find and cc_bulk_stream neither use nor update it.  Default 0. */
+  /* Membership filter of the largest component: two bitmaps of n bits each
+   * (n / 4 bytes of device memory).  The membership bitmap holds vertices
+   * proven connected to an anchor vertex, chosen as the root most sampled
+   * minibatch endpoints lead to; the touched bitmap holds both ends of every
+   * link.  1 = under the fused schedule an edge whose endpoints are both
+   * members is dropped without a find (it could only join a component with
+   * itself); 2 = that, and Bulk-Query answers without a find a pair of two
+   * members (1) and, while every update since the last reset went through
+   * the filtered fused schedule, a pair with an end outside the touched
+   * bitmap (0: that vertex never had an edge); its finds also add the
+   * endpoints they prove connected.  cc_labels uses the bitmaps whenever
+   * they exist.  Bits are set only from proofs, so results are unchanged.
+   * Choosing the anchor costs one single-block launch and one launch that
+   * refills the membership bitmap when the anchor changes (a pass over the
+   * parent array), before update calls 0, 1, 2, 4, 8, ... and every 64th
+   * call after a reset or load.  The split and contracting schedules,
+   * Bulk-Find and cc_bulk_stream neither use nor update the bitmaps.
+   * Default 0. */
   CC_OPT_FILTER = 12,
   /* Pairs per thread of Bulk-Query: 1, 2, 4 or 8, or 0 = as CC_OPT_ITEMS
-   * (default).  Queries gain from more pairs in flight per thread where the
-   * filtered update wants one edge per thread. */
+   * (default), for when queries and updates want different amounts of work
+   * in flight per thread. */
   CC_OPT_QUERY_ITEMS = 13
 };
 

@@ -47,7 +47,7 @@ namespace {
 
 constexpr int kPickThreads = 512;   // sampled edges per pick (two endpoints each)
 constexpr int kPickSlots = 2048;    // LDS hash table of sampled roots
-constexpr int kMemberCtlWords = 16;  // [0] anchor (-1: none), [1] clear request, [2] touched bitmap complete
+constexpr int kMemberCtlWords = 16;  // [0] anchor (-1: none), [1] refill request, [2] touched bitmap complete
 
 // Bitmap helpers (both bitmaps): the word holding v's bit, and v's bit in
 // it.  A word read before another thread set a bit only misses that bit (the

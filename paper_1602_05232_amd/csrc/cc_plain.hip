@@ -64,7 +64,7 @@ struct cc_graph {
   bool bf_ready = false;
   int64_t bf_seg0_entries = 0;   // allocated level-0 entries
   uint32_t* member = nullptr;    // membership bitmap of the filter, ceil(n / 32) words
-  int32_t* member_ctl = nullptr; // kMemberCtlWords: anchor, clear request, touched-complete flag
+  int32_t* member_ctl = nullptr; // kMemberCtlWords: anchor, refill request, touched-complete flag
   int64_t member_calls = 0;      // fused updates since the filter state was last reset
   bool pristine = true;          // no update or load since creation or the last reset
   bool touched_maybe_complete = false;  // the device's touched-complete flag may be set
