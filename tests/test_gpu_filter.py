@@ -88,7 +88,7 @@ def test_rmat_bits_are_proofs_and_the_anchor_is_the_giant(cc, opts):
     g.close()
 
 
-def test_anchor_moves_to_the_larger_component_and_the_bitmap_is_cleared(cc):
+def test_anchor_moves_to_the_larger_component_and_the_bitmap_is_refilled(cc):
     n = 1 << 15
     rng = np.random.default_rng(5)
     path = np.stack([np.arange(0, 1999), np.arange(1, 2000)], 1)          # component A: [0, 2000)
@@ -252,3 +252,33 @@ def test_replays_and_other_schedules_keep_queries_exact(cc):
         np.testing.assert_array_equal(g.labels().cpu().numpy(), ref.labels())
         rec.close()
         g.close()
+
+
+def test_stream_kernel_after_filtered_updates_keeps_answers_exact(cc):
+    """cc_bulk_stream applies minibatches without the bitmaps: afterwards the
+    touched bitmap is no longer trusted, and every answer stays exact."""
+    s = synth.rmat_stream(scale=13, size_lo=7, size_hi=12, qbatch=512)
+    half = s.num_batches // 2
+    g = cc.Graph(s.n, filter=2, hook=2)
+    ref = oracle.UnionFind(s.n)
+    for i in range(half):
+        ref.bulk_update(s.batch(i))
+        g.bulk_update(dev(s.batch(i)))
+        np.testing.assert_array_equal(g.bulk_query(dev(s.query(i))).cpu().numpy(), ref.bulk_query(s.query(i)))
+    assert g.filter_state()[1]
+    rest = range(half, s.num_batches)
+    edges = np.concatenate([s.batch(i) for i in rest])
+    pairs = np.concatenate([s.query(i) for i in rest])
+    eoff = torch.tensor(np.concatenate([[0], np.cumsum([len(s.batch(i)) for i in rest])]), dtype=torch.int64).cuda()
+    qoff = torch.tensor(np.concatenate([[0], np.cumsum([len(s.query(i)) for i in rest])]), dtype=torch.int64).cuda()
+    out = torch.empty(len(pairs), dtype=torch.uint8, device="cuda")
+    g.bulk_stream(dev(edges), eoff, dev(pairs), qoff, out)
+    want = np.concatenate([(ref.bulk_update(s.batch(i)), ref.bulk_query(s.query(i)))[1] for i in rest])
+    np.testing.assert_array_equal(out.cpu().numpy(), want)
+    assert not g.filter_state()[1]
+    check_bits(g, ref, "after the stream kernel")
+    q = np.random.default_rng(2).integers(0, s.n, size=(4096, 2)).astype(np.int32)
+    np.testing.assert_array_equal(g.bulk_query(dev(q)).cpu().numpy(), ref.bulk_query(q))
+    np.testing.assert_array_equal(g.labels().cpu().numpy(), ref.labels())
+    assert g.sync() == cc.cc.CC_OK
+    g.close()
