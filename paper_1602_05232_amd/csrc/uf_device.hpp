@@ -197,9 +197,16 @@ __device__ __forceinline__ int32_t link_roots(int32_t* parent, int32_t a, int32_
 // the loser's whole word (still a root, same rank), and a root's (rank, id)
 // only grows, so keys strictly increase along every parent path: no cycle.
 // A rank increment that loses a race is skipped; ranks only steer balance.
+// Step bound: an unfinished pass either finds that a tracked vertex stopped
+// being a root (once per vertex) or loses its CAS to a link of the loser or
+// to a rank increment (each at most once per vertex: at most n - 1 links and
+// n - 1 increments in a forest of n vertices), so a sound forest never needs
+// 3 * cap passes, while cap passes can be too few (n = 3: CAS lost to a link,
+// find, CAS lost to a link, find).
 __device__ __forceinline__ int32_t link_roots_rank(int32_t* parent, int32_t a, int32_t b, int32_t cap,
                                                    int* flags, int32_t* winner = nullptr) {
-  uint32_t steps = 0;
+  const uint64_t max_steps = 3ull * (uint64_t)(uint32_t)cap;
+  uint64_t steps = 0;
   while (a != b) {
     const int32_t wa = ld(parent + a), wb = ld(parent + b);
     if ((wa & kIdMask) != a) {
@@ -217,7 +224,7 @@ __device__ __forceinline__ int32_t link_roots_rank(int32_t* parent, int32_t a, i
         return lo;
       }
     }
-    if (++steps > (uint32_t)cap) {
+    if (++steps > max_steps) {
       raise_flag(flags, kFlagCorrupt);
       return -1;
     }

@@ -100,7 +100,7 @@ def pool_options(rng):
                 one_launch=int(rng.integers(2)))
 
 
-@pytest.mark.parametrize("seed", range(60))
+@pytest.mark.parametrize("seed", list(range(60)) + [140])  # 140: rank links on a 3-vertex graph in one block
 def test_random_pool_config(cc, seed):
     """Random graph mixes in one pool, several operations per graph in one
     run (so runs have several rounds), against one oracle per graph."""
@@ -135,3 +135,38 @@ def test_random_pool_config(cc, seed):
         assert pool.num_components(ids[g]) == refs[g].num_components()
     assert pool.sync() == cc.cc.CC_OK
     pool.close()
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 8])
+def test_rank_links_contend_on_tiny_graphs(cc, n):
+    """Union by rank with thousands of edges on a few vertices in one block:
+    a link retried after lost CAS races must not be taken for a cycle (its
+    step bound counts links and rank increments, not only vertices)."""
+    print("tiny rank contention: n=%d" % n, flush=True)
+    g = cc.Graph(n, hook=2, block=1024, items=2, grid_cap=1, compress_linked=1)
+    for rep in range(100):
+        g.reset()
+        e = synth.uniform_pairs(synth.key(321, n, rep), 0, 2048, n)
+        ref = oracle.UnionFind(n)
+        ref.bulk_update(e)
+        g.bulk_update(torch.from_numpy(e).cuda())
+        np.testing.assert_array_equal(g.labels().cpu().numpy(), ref.labels(), err_msg="rep %d" % rep)
+        assert g.sync() == cc.cc.CC_OK, "rep %d" % rep
+    g.close()
+    for one_launch in (0, 1):
+        pool = cc.Pool(64 * n, 64, hook=2, block=1024, items=2, grid_cap=1, one_launch=one_launch)
+        ids = [pool.add(n) for _ in range(64)]
+        for rep in range(20):
+            pool.reset_all()
+            ops, refs = [], []
+            for k, gid in enumerate(ids):
+                e = synth.uniform_pairs(synth.key(654, 64 * rep + k, n), 0, 256, n)
+                ref = oracle.UnionFind(n)
+                ref.bulk_update(e)
+                refs.append(ref)
+                ops.append((gid, cc.UPDATE, torch.from_numpy(e).cuda(), None))
+            pool.run(ops)
+            for gid, ref in zip(ids, refs):
+                np.testing.assert_array_equal(pool.labels(gid).cpu().numpy(), ref.labels())
+            assert pool.sync() == cc.cc.CC_OK, "one_launch %d rep %d" % (one_launch, rep)
+        pool.close()
