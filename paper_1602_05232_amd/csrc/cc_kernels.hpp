@@ -424,17 +424,19 @@ __global__ void k_query(int32_t* __restrict__ parent, const int2* __restrict__ p
     // and an anchor that is still alone when picked is linked by the update
     // that follows the pick).  So the touched words go first: a clear bit
     // settles the pair as 0, and membership words are read only for pairs
-    // whose ends have both had edges.
+    // whose ends have both had edges.  The second end's touched word is read
+    // only when the first end's bit is set: the query is bound by the rate of
+    // these L2 gathers, not by the extra dependent round.
     uint32_t mu[ITEMS], mv[ITEMS], tu[ITEMS], tv[ITEMS];
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
       mu[k] = mv[k] = 0u;
       tu[k] = tv[k] = ~0u;
-      if (lone && in_range(e[k], n)) {
-        tu[k] = bit_word(touched, e[k].x);
-        tv[k] = bit_word(touched, e[k].y);
-      }
+      if (lone && in_range(e[k], n)) tu[k] = bit_word(touched, e[k].x);
     }
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k)
+      if (lone && in_range(e[k], n) && bit_test(tu[k], e[k].x)) tv[k] = bit_word(touched, e[k].y);
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k)
       if (filt && in_range(e[k], n) && bit_test(tu[k], e[k].x) && bit_test(tv[k], e[k].y)) {
