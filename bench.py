@@ -280,8 +280,9 @@ def run_rmat(args):
             % (G, Gbig, Bs / 1e9, Eroof, upd_rate / Eroof))
         if opts.get("filter", 0):
             # ceilings of the membership filter's fast paths: an edge settled
-            # by its two membership words, a query by its two touched words
-            # (the cheapest case; a pair of two members reads two more), each
+            # by its two membership words, and a query pair priced the same
+            # (its first touched word alone settles a pair whose first end
+            # never had an edge; two touched ends take up to four words), each
             # plus its 8 streamed bytes
             words = (s.n + 31) // 32
             Gb = roofline.gather_rate(words)
@@ -291,8 +292,9 @@ def run_rmat(args):
                 "bitmap_words": words, "G_gathers_per_s_table_bitmap": Gb,
                 "E_filter_roof_edges_per_s": Ef, "update_frac_of_filter_roof": upd_rate / Ef,
                 "Q_filter_roof_per_s": Qf, "query_frac_of_filter_roof": qry_rate / Qf,
-                "note": "ceiling if every edge (query) were settled by two bitmap words: "
-                        "1/(2/G_b + 8/B_s) per item, G_b = gathers/s from a table of the bitmap's size"}
+                "note": "ceiling if every edge (query pair) were settled by two bitmap words: "
+                        "1/(2/G_b + 8/B_s) per item, G_b = gathers/s from a table of the bitmap's size; "
+                        "a query pair reads one to four words"}
             log("filter roofline: G(bitmap)=%.3g/s E_f=%.3g e/s (frac %.3f) Q_f=%.3g q/s (frac %.3f)"
                 % (Gb, Ef, upd_rate / Ef, Qf, qry_rate / Qf))
     g.close()
