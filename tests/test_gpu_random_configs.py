@@ -139,9 +139,10 @@ def test_random_pool_config(cc, seed):
 
 @pytest.mark.parametrize("n", [2, 3, 4, 5, 8])
 def test_rank_links_contend_on_tiny_graphs(cc, n):
-    """Union by rank with thousands of edges on a few vertices in one block:
-    a link retried after lost CAS races must not be taken for a cycle (its
-    step bound counts links and rank increments, not only vertices)."""
+    """Union by rank with thousands of edges on a few vertices in one block
+    (plain launches, the one-launch stream form, pools): a link retried after
+    lost CAS races must not be taken for a cycle (its step bound counts links
+    and rank increments, not only vertices)."""
     print("tiny rank contention: n=%d" % n, flush=True)
     g = cc.Graph(n, hook=2, block=1024, items=2, grid_cap=1, compress_linked=1)
     for rep in range(100):
@@ -152,6 +153,23 @@ def test_rank_links_contend_on_tiny_graphs(cc, n):
         g.bulk_update(torch.from_numpy(e).cuda())
         np.testing.assert_array_equal(g.labels().cpu().numpy(), ref.labels(), err_msg="rep %d" % rep)
         assert g.sync() == cc.cc.CC_OK, "rep %d" % rep
+    # the one-launch stream form: four minibatches and their queries per launch
+    for rep in range(20):
+        g.reset()
+        e = synth.uniform_pairs(synth.key(987, n, rep), 0, 4 * 1024, n)
+        q = synth.uniform_pairs(synth.key(988, n, rep), 0, 4 * 64, n)
+        eo = torch.arange(0, 4 * 1024 + 1, 1024, dtype=torch.int64, device="cuda")
+        qo = torch.arange(0, 4 * 64 + 1, 64, dtype=torch.int64, device="cuda")
+        out = torch.empty(len(q), dtype=torch.uint8, device="cuda")
+        g.bulk_stream(torch.from_numpy(e).cuda(), eo, torch.from_numpy(q).cuda(), qo, out)
+        ref = oracle.UnionFind(n)
+        want = []
+        for b in range(4):
+            ref.bulk_update(e[1024 * b:1024 * (b + 1)])
+            want.append(ref.bulk_query(q[64 * b:64 * (b + 1)]))
+        np.testing.assert_array_equal(out.cpu().numpy(), np.concatenate(want), err_msg="stream rep %d" % rep)
+        np.testing.assert_array_equal(g.labels().cpu().numpy(), ref.labels(), err_msg="stream rep %d" % rep)
+        assert g.sync() == cc.cc.CC_OK, "stream rep %d" % rep
     g.close()
     for one_launch in (0, 1):
         pool = cc.Pool(64 * n, 64, hook=2, block=1024, items=2, grid_cap=1, one_launch=one_launch)
