@@ -425,8 +425,8 @@ __global__ void k_query(int32_t* __restrict__ parent, const int2* __restrict__ p
     // that follows the pick).  So the touched words go first: a clear bit
     // settles the pair as 0, and membership words are read only for pairs
     // whose ends have both had edges.  The second end's touched word is read
-    // only when the first end's bit is set: the query is bound by the rate of
-    // these L2 gathers, not by the extra dependent round.
+    // only when the first end's bit is set: fewer gathers measured faster
+    // than one dependent round fewer.
     uint32_t mu[ITEMS], mv[ITEMS], tu[ITEMS], tv[ITEMS];
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
