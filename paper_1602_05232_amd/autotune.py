@@ -44,7 +44,7 @@ def plain_candidates(quick=False):
     out += [dict(update_mode=1, block=b, items=0) for b in (256, 1024)]
     # the membership filter's form settles open edges per block, so it
     # prefers fewer, longer-lived blocks
-    for block, gc, f, hook, qi in itertools.product((256, 512), (512, 768, 1024, 1280), (1, 2), (0, 1, 2), (0, 4)):
+    for block, gc, f, hook, qi in itertools.product((256, 512), (512, 768, 1024, 1280), (1, 2), (0, 1, 2), (0, 2, 4)):
         out.append(dict(update_mode=0, block=block, items=1, grid_cap=gc, compress_linked=0, hook=hook, filter=f,
                         query_items=qi))
     if quick:

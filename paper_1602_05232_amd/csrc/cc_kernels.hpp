@@ -427,30 +427,45 @@ __global__ void k_query(int32_t* __restrict__ parent, const int2* __restrict__ p
     // whose ends have both had edges.  The second end's touched word is read
     // only when the first end's bit is set: fewer gathers measured faster
     // than one dependent round fewer.
+    // Every lane issues each round's loads (a lane that needs no word reads
+    // word 0, one line shared by the wavefront), so with several items per
+    // thread the loads of a round are in flight together instead of one
+    // per-item branch at a time.
     uint32_t mu[ITEMS], mv[ITEMS], tu[ITEMS], tv[ITEMS];
+    bool ok[ITEMS];
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
+      ok[k] = in_range(e[k], n);
       mu[k] = mv[k] = 0u;
       tu[k] = tv[k] = ~0u;
-      if (lone && in_range(e[k], n)) tu[k] = bit_word(touched, e[k].x);
     }
+    if (lone) {
 #pragma unroll
-    for (int k = 0; k < ITEMS; ++k)
-      if (lone && in_range(e[k], n) && bit_test(tu[k], e[k].x)) tv[k] = bit_word(touched, e[k].y);
+      for (int k = 0; k < ITEMS; ++k) tu[k] = bit_word(touched, ok[k] ? e[k].x : 0);
 #pragma unroll
-    for (int k = 0; k < ITEMS; ++k)
-      if (filt && in_range(e[k], n) && bit_test(tu[k], e[k].x) && bit_test(tv[k], e[k].y)) {
-        mu[k] = bit_word(member, e[k].x);
-        mv[k] = bit_word(member, e[k].y);
+      for (int k = 0; k < ITEMS; ++k) {
+        const bool need = ok[k] && bit_test(tu[k], e[k].x);
+        const uint32_t w = bit_word(touched, need ? e[k].y : 0);
+        tv[k] = need ? w : 0u;
       }
+    }
+    if (filt) {
+#pragma unroll
+      for (int k = 0; k < ITEMS; ++k) {
+        const bool need = ok[k] && bit_test(tu[k], e[k].x) && bit_test(tv[k], e[k].y);
+        const uint32_t wu = bit_word(member, need ? e[k].x : 0);
+        const uint32_t wv = bit_word(member, need ? e[k].y : 0);
+        mu[k] = need ? wu : 0u;
+        mv[k] = need ? wv : 0u;
+      }
+    }
     int32_t pu[ITEMS], pv[ITEMS];
     uint8_t a[ITEMS];
     unsigned open = 0;
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
-      pu[k] = pv[k] = 0;
       a[k] = 0;
-      if (!in_range(e[k], n)) {
+      if (!ok[k]) {
         raise_flag(flags, kFlagRange);
         continue;
       }
@@ -466,8 +481,12 @@ __global__ void k_query(int32_t* __restrict__ parent, const int2* __restrict__ p
         continue;
       }
       open |= 1u << k;
-      pu[k] = ldp<R>(parent + u);
-      pv[k] = ldp<R>(parent + v);
+    }
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {  // vertex 0 for the items already answered
+      const bool o = (open >> k) & 1u;
+      pu[k] = ldp<R>(parent + (o ? e[k].x : 0));
+      pv[k] = ldp<R>(parent + (o ? e[k].y : 0));
     }
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
