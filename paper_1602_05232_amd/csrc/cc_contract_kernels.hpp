@@ -96,7 +96,7 @@ __global__ void k_contract(int32_t* __restrict__ parent, const int2* __restrict_
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
       const int64_t i = t0 + (int64_t)k * B + tid;
-      r[k] = i < e1 ? edges[i] : make_int2(0, 0);  // padding: a self-loop on vertex 0
+      r[k] = i < e1 ? ld_stream_pair(edges, i) : make_int2(0, 0);  // padding: a self-loop on vertex 0
     }
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {

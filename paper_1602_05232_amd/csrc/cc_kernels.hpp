@@ -191,7 +191,7 @@ __global__ void k_update_fused(int32_t* __restrict__ parent, const int2* __restr
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
       const int64_t i = t0 + (int64_t)k * blockDim.x + threadIdx.x;
-      e[k] = i < m ? edges[i] : make_int2(0, 0);  // padding: a self-loop on vertex 0
+      e[k] = i < m ? ld_stream_pair(edges, i) : make_int2(0, 0);  // padding: a self-loop on vertex 0
     }
     uint32_t mu[ITEMS], mv[ITEMS];
 #pragma unroll
@@ -286,7 +286,7 @@ __global__ void k_filter(int32_t* __restrict__ parent, const int2* __restrict__ 
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
       const int64_t i = t0 + (int64_t)k * blockDim.x + threadIdx.x;
-      int2 e = i < m ? edges[i] : make_int2(0, 0);
+      int2 e = i < m ? ld_stream_pair(edges, i) : make_int2(0, 0);
       if (!in_range(e, n)) {
         raise_flag(flags, kFlagRange);
         e = make_int2(0, 0);
@@ -417,7 +417,7 @@ __global__ void k_query(int32_t* __restrict__ parent, const int2* __restrict__ p
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
       const int64_t i = t0 + (int64_t)k * blockDim.x + threadIdx.x;
-      e[k] = i < q ? pairs[i] : make_int2(0, 0);
+      e[k] = i < q ? ld_stream_pair(pairs, i) : make_int2(0, 0);
     }
     // While the touched bitmap is complete it holds every vertex that has
     // had an edge, members included (a member is connected to the anchor,

@@ -70,7 +70,7 @@ __device__ __forceinline__ void pool_tile(const OpDesc& op, uint32_t t, int32_t*
 #pragma unroll
   for (int k = 0; k < ITEMS; ++k) {
     const int64_t i = t0 + (int64_t)k * blockDim.x + threadIdx.x;
-    e[k] = i < op.count ? op.items[i] : make_int2(0, 0);
+    e[k] = i < op.count ? ld_stream_pair(op.items, i) : make_int2(0, 0);
   }
   if (op.kind == 0) {
     int32_t hk[ITEMS];

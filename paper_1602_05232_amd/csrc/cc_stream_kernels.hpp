@@ -29,7 +29,7 @@ __global__ void k_stream(int32_t* __restrict__ parent, int64_t batches, const in
   for (int64_t b = 0; b < batches; ++b) {
     const int64_t e1 = eoff[b + 1];
     for (int64_t i = eoff[b] + gtid; i < e1; i += gsize) {
-      const int2 e = edges[i];
+      const int2 e = ld_stream_pair(edges, i);
       if (!in_range(e, n)) {
         raise_flag(flags, kFlagRange);
         continue;
@@ -44,7 +44,7 @@ __global__ void k_stream(int32_t* __restrict__ parent, int64_t batches, const in
     if (!grid_sync(bar, gen, flags, spin_limit)) break;
     const int64_t q1 = qoff[b + 1];
     for (int64_t i = qoff[b] + gtid; i < q1; i += gsize) {
-      const int2 e = pairs[i];
+      const int2 e = ld_stream_pair(pairs, i);
       uint8_t a = 0;
       if (!in_range(e, n)) {
         raise_flag(flags, kFlagRange);
