@@ -35,7 +35,7 @@ extern "C" {
 typedef struct cc_pool cc_pool;
 
 /* One operation of a cc_pool_run list.  kind 0 = Bulk-Update: `items` holds
- * count edges, device int32[count][2], graph-local ids.  kind 1 = Bulk-Query:
+ * count edges, device int32[count][2] (8-byte aligned), graph-local ids.  kind 1 = Bulk-Query:
  * `items` holds count pairs and `out` receives count uint8 answers (device),
  * in input order. */
 typedef struct {

@@ -145,6 +145,8 @@ def _pairs_ptr(t: torch.Tensor, what: str) -> int:
         raise TypeError("%s must be a CUDA int32 tensor" % what)
     if t.numel() and not (t.dim() == 2 and t.shape[1] == 2 and t.is_contiguous()):
         raise ValueError("%s must be a contiguous [k, 2] tensor" % what)
+    if t.numel() and t.data_ptr() % 8:
+        raise ValueError("%s must start on an 8-byte boundary (one pair per 8-byte load)" % what)
     return t.data_ptr()
 
 

@@ -35,6 +35,9 @@ struct DeviceGuard {
   }
 };
 
+// Edge and pair arrays are read 8 bytes (one pair) per load.
+inline bool misaligned8(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 7u) != 0; }
+
 inline unsigned blocks_for(int64_t items, int64_t per_block, int cap) {
   int64_t b = (items + per_block - 1) / per_block;
   if (b < 1) b = 1;

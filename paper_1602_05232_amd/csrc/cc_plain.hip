@@ -542,8 +542,8 @@ extern "C" int cc_reset(cc_graph* g) {
 }
 
 extern "C" int cc_bulk_update(cc_graph* g, const int32_t* edges, int64_t m) {
-  if (!g || m < 0 || (m > 0 && !edges)) {
-    cc_set_error("cc_bulk_update: invalid argument");
+  if (!g || m < 0 || (m > 0 && (!edges || cc::misaligned8(edges)))) {
+    cc_set_error("cc_bulk_update: invalid argument (edges must be 8-byte aligned device memory)");
     return CC_EINVAL;
   }
   if (m == 0) return CC_OK;
@@ -626,8 +626,8 @@ extern "C" int cc_bulk_update(cc_graph* g, const int32_t* edges, int64_t m) {
 }
 
 extern "C" int cc_bulk_query(cc_graph* g, const int32_t* pairs, int64_t q, uint8_t* out) {
-  if (!g || q < 0 || (q > 0 && (!pairs || !out))) {
-    cc_set_error("cc_bulk_query: invalid argument");
+  if (!g || q < 0 || (q > 0 && (!pairs || !out || cc::misaligned8(pairs)))) {
+    cc_set_error("cc_bulk_query: invalid argument (pairs must be 8-byte aligned device memory)");
     return CC_EINVAL;
   }
   if (q == 0) return CC_OK;
@@ -915,8 +915,10 @@ int launch_stream(cc_graph* g, int64_t batches, const int32_t* edges, const int6
 
 extern "C" int cc_bulk_stream(cc_graph* g, int64_t batches, const int32_t* edges, const int64_t* eoff,
                               const int32_t* pairs, const int64_t* qoff, uint8_t* out, int64_t max_items) {
-  if (!g || batches < 0 || max_items < 1 || (batches > 0 && (!edges || !eoff || !pairs || !qoff || !out))) {
-    cc_set_error("cc_bulk_stream: invalid argument");
+  if (!g || batches < 0 || max_items < 1 ||
+      (batches > 0 && (!edges || !eoff || !pairs || !qoff || !out || cc::misaligned8(edges) ||
+                       cc::misaligned8(pairs)))) {
+    cc_set_error("cc_bulk_stream: invalid argument (edges and pairs must be 8-byte aligned device memory)");
     return CC_EINVAL;
   }
   if (g->capturing) {

@@ -451,7 +451,7 @@ extern "C" int cc_pool_run(cc_pool* p, const cc_op* ops, int32_t num_ops) {
   for (int32_t i = 0; i < num_ops; ++i) {
     const cc_op& o = ops[i];
     if (!valid_graph(p, o.graph) || (o.kind != 0 && o.kind != 1) || o.count < 0 ||
-        (o.count > 0 && (!o.items || (o.kind == 1 && !o.out)))) {
+        (o.count > 0 && (!o.items || cc::misaligned8(o.items) || (o.kind == 1 && !o.out)))) {
       cc_set_error("cc_pool_run: operation %d is invalid", i);
       return CC_EINVAL;
     }

@@ -228,6 +228,42 @@ def test_argument_errors(cc):
     g.close()
 
 
+def test_misaligned_item_arrays_are_rejected(cc):
+    """Edge and pair arrays are read one 8-byte pair per load: an array that
+    does not start on an 8-byte boundary is an argument error at every entry
+    point, and nothing runs."""
+    import ctypes
+    from paper_1602_05232_amd import cc as ccmod
+    L = cc.lib()
+    g = cc.Graph(16)
+    buf = torch.arange(10, dtype=torch.int32, device="cuda")
+    bad = ctypes.c_void_p(buf.data_ptr() + 4)
+    good = ctypes.c_void_p(buf.data_ptr())
+    out = torch.zeros(8, dtype=torch.uint8, device="cuda")
+    eo = torch.tensor([0, 4], dtype=torch.int64, device="cuda")
+    assert L.cc_bulk_update(g.handle, bad, 4) == cc.cc.CC_EINVAL
+    assert L.cc_bulk_query(g.handle, bad, 4, out.data_ptr()) == cc.cc.CC_EINVAL
+    assert L.cc_bulk_stream(g.handle, 1, bad, eo.data_ptr(), good, eo.data_ptr(), out.data_ptr(), 4) == \
+        cc.cc.CC_EINVAL
+    assert L.cc_bulk_stream(g.handle, 1, good, eo.data_ptr(), bad, eo.data_ptr(), out.data_ptr(), 4) == \
+        cc.cc.CC_EINVAL
+    with pytest.raises(ValueError):
+        g.bulk_update(buf[1:9].view(4, 2))
+    assert g.num_components() == 16
+    assert g.sync() == cc.cc.CC_OK
+    g.close()
+    pool = cc.Pool(32, 2)
+    gid = pool.add(16)
+    ops = (ccmod.CcOp * 1)()
+    ops[0].graph, ops[0].kind, ops[0].count, ops[0].items, ops[0].out = gid, 0, 4, bad.value, None
+    assert L.cc_pool_run(pool._h, ops, 1) == cc.cc.CC_EINVAL
+    with pytest.raises(ValueError):
+        pool.run([(gid, cc.UPDATE, buf[1:9].view(4, 2), None)])
+    assert pool.num_components(gid) == 16
+    assert pool.sync() == cc.cc.CC_OK
+    pool.close()
+
+
 def test_linking_order_is_fixed_until_reset(cc):
     """Rank bits live in root words and the label passes assume one order, so
     the order may change only on a fresh forest; a rejected update leaves the
