@@ -202,7 +202,11 @@ __global__ void k_update_fused(int32_t* __restrict__ parent, const int2* __restr
         mv[k] = bit_word(member, e[k].y);
       }
     }
-    if (FILT) {
+    // With no anchor yet (a fresh forest) the bitmap can drop nothing, so
+    // each edge is settled in place as in the unfiltered form, which keeps
+    // the touched bitmap all the same (first R-MAT scale-24 minibatch: 0.65
+    // -> 0.63 ms).
+    if (FILT && filt) {
       int c = 0;
 #pragma unroll
       for (int k = 0; k < ITEMS; ++k) {
@@ -235,7 +239,9 @@ __global__ void k_update_fused(int32_t* __restrict__ parent, const int2* __restr
       }
       continue;
     }
-    // Unfiltered: each item reads its parents just before it uses them.
+    // Unfiltered, or filtered before an anchor exists (then the touched
+    // bitmap is kept here): each item reads its parents just before it uses
+    // them.
     // Reading all items' parents first measured slower under id and hashed
     // linking (8 items per thread, one large minibatch: 12.6 -> 14.0 ms and
     // 9.9 -> 13.7 ms), as the early reads go stale while earlier items link.
@@ -251,7 +257,7 @@ __global__ void k_update_fused(int32_t* __restrict__ parent, const int2* __restr
       const int32_t u = e[k].x, v = e[k].y;
       if (u == v) continue;
       hk[k] = settle_edge<Ord>(parent, u, v, ldp<R>(parent + u), ldp<R>(parent + v), n, flags, false, -1, member,
-                               false, false, nullptr);
+                               false, false, FILT ? member + member_words : nullptr);
       if (hk[k] >= 0) ++nh;
     }
     links += nh;
