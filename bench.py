@@ -538,28 +538,17 @@ def run_serve(args):
     n = 1 << scale
     seed = synth.BASE_SEED + 5
     t = time.perf_counter()
-    kind_u = synth.unit_doubles(synth.key(seed, 0, synth.P_REQ_TYPE), 0, R)
-    strm = (synth.unit_doubles(synth.key(seed, 0, synth.P_REQ_STREAM), 0, R) * S).astype(np.int64)
-    sizes = np.floor(np.exp2(8 + 14 * synth.unit_doubles(synth.key(seed, 0, synth.P_REQ_SIZE), 0, R))).astype(np.int64)
-    perms = {}
-    cursor = np.zeros(S, np.int64)
     reqs = []
     tot_e = tot_q = 0
-    for i in range(R):
-        st, size = int(strm[i]), int(sizes[i])
-        if kind_u[i] < 0.7:
-            if st not in perms:
-                perms[st] = synth.permutation(synth.key(seed, st + 1, synth.P_PERM), n)
-            items = synth.rmat_edges(synth.key(seed, st + 1, synth.P_EDGES), int(cursor[st]), size, scale, n,
-                                     perms[st])
-            cursor[st] += size
-            reqs.append(serve.Request(i, st, serve.UPDATE, 0.0, torch.from_numpy(items).cuda(), None, size))
-            tot_e += size
+    for r in synth.serving_trace(S=S, scale=scale, R=R, seed=seed):
+        items = torch.from_numpy(r.items).cuda()
+        if r.kind == 0:
+            reqs.append(serve.Request(r.rid, r.stream, serve.UPDATE, 0.0, items, None, r.size))
+            tot_e += r.size
         else:
-            items = synth.uniform_pairs(synth.key(seed, st + 1, synth.P_QUERIES), i, size, n)
-            reqs.append(serve.Request(i, st, serve.QUERY, 0.0, torch.from_numpy(items).cuda(),
-                                      torch.zeros(size, dtype=torch.uint8, device="cuda"), size))
-            tot_q += size
+            reqs.append(serve.Request(r.rid, r.stream, serve.QUERY, 0.0, items,
+                                      torch.zeros(r.size, dtype=torch.uint8, device="cuda"), r.size))
+            tot_q += r.size
     torch.cuda.synchronize()
     log("serving trace: %d requests over %d streams of n=2^%d, %d update edges, %d query pairs (%.1fs)"
         % (R, S, scale, tot_e, tot_q, time.perf_counter() - t))

@@ -148,6 +148,17 @@ inline int64_t coop_limit(int per_cu, int cus) {
   return (int64_t)(per_cu > 1 ? per_cu - 1 : 1) * cus;
 }
 
+// Cooperative launches of this library never overlap on a device.  Each
+// sizes its grid to nearly fill the device and waits at device-wide barriers
+// until every block is resident, so two of them running at once (different
+// graphs or pool runs on different streams) could each hold compute units
+// the other waits for.  coop_before(stream) makes `stream` wait (on the
+// device, without blocking the host) for the last cooperative launch issued
+// on another stream of the current device; coop_after(stream) records the
+// launch just issued on `stream` as the last one.  Thread safe.
+int coop_before(hipStream_t stream);
+int coop_after(hipStream_t stream);
+
 // Items per thread for a launch over m items: the requested value, or with
 // 0 the largest of 8, 4, 2, 1 that still gives at least 2048 blocks.
 inline int pick_items(int requested, int64_t m, int block) {

@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "../../include/cc.h"
@@ -34,6 +35,42 @@ void cc_set_error(const char* fmt, ...) {
 }
 
 extern "C" const char* cc_last_error(void) { return g_err; }
+
+namespace cc {
+namespace {
+struct CoopState {
+  hipEvent_t last = nullptr;     // recorded after the last cooperative launch
+  hipStream_t stream = nullptr;  // the stream it was issued on
+  bool any = false;
+};
+constexpr int kMaxDevices = 64;
+std::mutex g_coop_mu;
+CoopState g_coop[kMaxDevices];
+}  // namespace
+
+int coop_before(hipStream_t stream) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return CC_OK;
+  std::lock_guard<std::mutex> lk(g_coop_mu);
+  CoopState& c = g_coop[dev];
+  if (c.any && c.stream != stream) HIP_TRY(hipStreamWaitEvent(stream, c.last, 0));
+  return CC_OK;
+}
+
+int coop_after(hipStream_t stream) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return CC_OK;
+  std::lock_guard<std::mutex> lk(g_coop_mu);
+  CoopState& c = g_coop[dev];
+  if (!c.last) HIP_TRY(hipEventCreateWithFlags(&c.last, hipEventDisableTiming | hipEventDisableSystemFence));
+  HIP_TRY(hipEventRecord(c.last, stream));
+  c.stream = stream;
+  c.any = true;
+  return CC_OK;
+}
+}  // namespace cc
 
 extern "C" const char* cc_strerror(int code) {
   switch (code) {
@@ -71,6 +108,11 @@ struct cc_graph {
   int64_t live_cap = 0;
   int64_t updates = 0;
   bool capturing = false;
+  // effect of the calls recorded so far in the current capture on the
+  // forest: a reset was recorded; updates recorded since the last reset (or
+  // since the capture began)
+  bool cap_reset = false;
+  int64_t cap_updates = 0;
   cc::Tuning tune;
 };
 
@@ -79,6 +121,10 @@ struct cc_exec {
   hipStream_t stream = nullptr;
   int device = 0;
   cc_graph* graph = nullptr;  // the graph it was captured on
+  int hook = 0;               // linking order the recorded kernels were built for
+  bool resets = false;        // the recording holds a reset ...
+  int64_t updates = 0;        // ... and this many updates after its last reset (or in all)
+  const uint32_t* member = nullptr;  // the filter bitmaps the recorded kernels keep (null: none)
 };
 
 namespace {
@@ -348,8 +394,10 @@ int launch_bulk_find_t(cc_graph* g, const int2* items, int64_t count, uint8_t* o
   int* flags = g->flags;
   unsigned spin = (unsigned)g->tune.spin_limit;
   void* args[] = {&parent, &items, &count, &n, &out, &sc, &slots, &flags, &spin};
+  if (const int crc = cc::coop_before(g->stream)) return crc;
   HIP_TRY(hipLaunchCooperativeKernel((const void*)k_bulk_find<KIND, Ord>, dim3((unsigned)grid), dim3(block), args,
                                      0, g->stream));
+  if (const int crc = cc::coop_after(g->stream)) return crc;
   return CC_OK;
 }
 
@@ -395,8 +443,10 @@ int launch_contract_t(cc_graph* g, const int2* e, int64_t m) {
   int* flags = g->flags;
   unsigned spin = (unsigned)g->tune.spin_limit;
   void* args[] = {&parent, &e, &m, &n, &list, &seg_cap, &ctl, &slots, &flags, &spin};
+  if (const int crc = cc::coop_before(g->stream)) return crc;
   HIP_TRY(hipLaunchCooperativeKernel((const void*)k_contract<Ord>, dim3((unsigned)grid), dim3(256), args, 0,
                                      g->stream));
+  if (const int crc = cc::coop_after(g->stream)) return crc;
   return CC_OK;
 }
 
@@ -538,6 +588,10 @@ extern "C" int cc_reset(cc_graph* g) {
   if (!g) return CC_EINVAL;
   DeviceGuard dg(g->device);
   g->updates = 0;
+  if (g->capturing) {
+    g->cap_reset = true;
+    g->cap_updates = 0;
+  }
   return launch_init(g);
 }
 
@@ -613,6 +667,7 @@ extern "C" int cc_bulk_update(cc_graph* g, const int32_t* edges, int64_t m) {
   }
   g->updates++;
   g->pristine = false;
+  if (g->capturing) g->cap_updates++;
   if (g->tune.compress_every > 0 && g->updates % g->tune.compress_every == 0) {
     if (ranked)
       hipLaunchKernelGGL(k_compress_all<true>, dim3(vertex_blocks(g)), dim3(256), 0, g->stream, g->parent,
@@ -837,6 +892,8 @@ extern "C" int cc_capture_begin(cc_graph* g) {
   if (rc != CC_OK) return rc;
   HIP_TRY(hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal));
   g->capturing = true;
+  g->cap_reset = false;
+  g->cap_updates = 0;
   return CC_OK;
 }
 
@@ -861,15 +918,50 @@ extern "C" int cc_capture_end(cc_graph* g, cc_exec** out) {
   x->stream = g->stream;
   x->device = g->device;
   x->graph = g;
+  x->hook = g->tune.hook;
+  x->resets = g->cap_reset;
+  x->updates = g->cap_updates;
+  x->member = g->member;
   *out = x;
   return CC_OK;
 }
 
 extern "C" int cc_exec_launch(cc_exec* x) {
   if (!x) return CC_EINVAL;
+  cc_graph* g = x->graph;
+  // The recorded kernels walk and link the forest under the linking order
+  // of the capture; a forest built under another order (rank bits in root
+  // words, other priorities) must not meet them.
+  if (g->tune.hook != x->hook) {
+    cc_set_error("cc_exec_launch: the graph's linking order changed since the capture");
+    return CC_EINVAL;
+  }
+  if (g->capturing) {
+    cc_set_error("cc_exec_launch: not allowed while the graph is capturing");
+    return CC_EINVAL;
+  }
   DeviceGuard dg(x->device);
   HIP_TRY(hipGraphLaunch(x->exec, x->stream));
-  x->graph->touched_maybe_complete = true;  // the replay may have reset the graph
+  // The forest afterwards is what the recording leaves: no links only if it
+  // resets and records no update after that, or if it neither resets nor
+  // updates and the forest had none.
+  if (x->resets) {
+    g->pristine = x->updates == 0;
+    g->updates = x->updates;
+  } else if (x->updates > 0) {
+    g->pristine = false;
+    g->updates += x->updates;
+  }
+  // Filter bitmaps allocated after the capture were not kept by the
+  // recorded kernels: after a recorded reset their bits are no proofs about
+  // the new forest, and recorded updates may have linked vertices the
+  // touched bitmap does not hold.
+  if (g->member && g->member != x->member) {
+    if (x->resets) member_reset(g, x->updates == 0 ? 1 : 0);
+    else if (x->updates > 0) member_touched_invalid(g);
+    HIP_TRY(hipGetLastError());
+  }
+  g->touched_maybe_complete = true;  // the replay may have reset the graph
   return CC_OK;
 }
 
@@ -906,8 +998,10 @@ int launch_stream(cc_graph* g, int64_t batches, const int32_t* edges, const int6
   unsigned* bar = g->gbar;
   unsigned spin = (unsigned)g->tune.spin_limit;
   void* args[] = {&parent, &batches, &e, &eoff, &p, &qoff, &out, &n, &slots, &flags, &bar, &spin};
+  if (const int crc = cc::coop_before(g->stream)) return crc;
   HIP_TRY(hipLaunchCooperativeKernel((const void*)k_stream<Ord>, dim3((unsigned)grid), dim3(block), args, 0,
                                      g->stream));
+  if (const int crc = cc::coop_after(g->stream)) return crc;
   return CC_OK;
 }
 

@@ -26,9 +26,10 @@ struct PoolGraph {
   bool used = false;
 };
 
-// One run in flight: its descriptors, and the list of roots its updates
-// linked (compressed after each round).  A slot is reused only after its
-// run has completed, so runs on different streams never share a list.
+// One run in flight: its descriptors, the list of roots its updates linked
+// (compressed after each round), and the device-wide barrier of its
+// one-launch form.  A slot is reused only after its run has completed, so
+// runs on different streams never share a list or a barrier.
 struct RingSlot {
   OpDesc* host = nullptr;  // pinned staging
   OpDesc* dev = nullptr;
@@ -38,6 +39,7 @@ struct RingSlot {
   int32_t* meta_host = nullptr;  // one-launch form: round starts, then round tiles
   int32_t* meta_dev = nullptr;
   int64_t meta_cap = 0;
+  unsigned* bar = nullptr;    // kBarWords, allocated on the first one-launch run
   hipEvent_t done = nullptr;
   bool pending = false;
 };
@@ -57,7 +59,6 @@ struct cc_pool {
   int32_t* staging = nullptr;       // device image buffer for save / load
   int64_t staging_cap = 0;
   unsigned long long* check = nullptr;  // [0] bad entries, [1] roots (image check)
-  unsigned* bar = nullptr;              // device-wide barrier of the one-launch form
   int2* table = nullptr;                // (base, n) of the graphs in use, for cc_pool_reset_all
   std::vector<int2> table_host;
   bool table_stale = true;              // graphs added or removed since the table was uploaded
@@ -100,7 +101,7 @@ void give_gap(cc_pool* p, int64_t base, int64_t n) {
   }
 }
 
-int reserve_slot(cc_pool* p, int64_t count, bool record, RingSlot** out) {
+int reserve_slot(cc_pool* p, int64_t count, bool record, bool one_launch, RingSlot** out) {
   RingSlot* s = &p->ring[p->ring_next];
   p->ring_next = (p->ring_next + 1) % kRing;
   if (s->pending) {
@@ -128,6 +129,11 @@ int reserve_slot(cc_pool* p, int64_t count, bool record, RingSlot** out) {
       return CC_ENOMEM;
     }
     HIP_TRY(hipMemsetAsync(s->ctl, 0, 64, p->stream));
+  }
+  if (one_launch && !s->bar && hipMalloc((void**)&s->bar, kBarWords * sizeof(unsigned)) != hipSuccess) {
+    s->bar = nullptr;
+    cc_set_error("cc_pool_run: barrier allocation failed");
+    return CC_ENOMEM;
   }
   *out = s;
   return CC_OK;
@@ -158,7 +164,7 @@ int launch_rounds_t(cc_pool* p, const RingSlot* s, int rounds, uint32_t max_tile
   HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device));
   int64_t grid = std::min<int64_t>(std::min<int64_t>(max_tiles, cc::coop_limit(per_cu, cus)), p->tune.grid_cap);
   grid = std::max<int64_t>(grid, 1);
-  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, p->stream, p->bar, kBarWords);
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, p->stream, s->bar, kBarWords);
   HIP_TRY(hipGetLastError());
   const OpDesc* ops = s->dev;
   const int32_t* rstart = s->meta_dev;
@@ -166,11 +172,13 @@ int launch_rounds_t(cc_pool* p, const RingSlot* s, int rounds, uint32_t max_tile
   int32_t* arena = p->arena;
   unsigned long long* glinks = p->glinks;
   int* flags = p->flags;
-  unsigned* bar = p->bar;
+  unsigned* bar = s->bar;
   unsigned spin = (unsigned)p->tune.spin_limit;
   void* args[] = {&ops, &rstart, &rtiles, &rounds, &arena, &glinks, &flags, &bar, &spin};
+  if (const int crc = cc::coop_before(p->stream)) return crc;
   HIP_TRY(hipLaunchCooperativeKernel((const void*)k_pool_rounds<ITEMS, HOOK, HALVE>, dim3((unsigned)grid), dim3(B),
                                      args, 0, p->stream));
+  if (const int crc = cc::coop_after(p->stream)) return crc;
   return CC_OK;
 }
 
@@ -253,7 +261,6 @@ extern "C" cc_pool* cc_pool_create(int64_t capacity, int32_t max_graphs) {
     (void)hipFree(p->arena);
     (void)hipFree(p->glinks);
     (void)hipFree(p->flags);
-    (void)hipFree(p->bar);
     (void)hipFree(p->table);
     delete p;
     return nullptr;
@@ -262,7 +269,6 @@ extern "C" cc_pool* cc_pool_create(int64_t capacity, int32_t max_graphs) {
   if (hipMalloc(&p->arena, (size_t)capacity * 4) != hipSuccess) return fail("arena");
   if (hipMalloc(&p->glinks, (size_t)max_graphs * kPoolLinkStride * 8) != hipSuccess) return fail("links");
   if (hipMalloc(&p->flags, 64) != hipSuccess) return fail("flags");
-  if (hipMalloc(&p->bar, kBarWords * sizeof(unsigned)) != hipSuccess) return fail("bar");
   if (hipMalloc(&p->table, (size_t)max_graphs * sizeof(int2)) != hipSuccess) return fail("table");
   if (hipMemsetAsync(p->flags, 0, 64, p->stream) != hipSuccess) return fail("memset");
   if (hipMemsetAsync(p->glinks, 0, (size_t)max_graphs * kPoolLinkStride * 8, p->stream) != hipSuccess)
@@ -285,6 +291,7 @@ extern "C" int cc_pool_destroy(cc_pool* p) {
     if (s.ctl) (void)hipFree(s.ctl);
     if (s.meta_host) (void)hipHostFree(s.meta_host);
     if (s.meta_dev) (void)hipFree(s.meta_dev);
+    if (s.bar) (void)hipFree(s.bar);
     if (s.done) (void)hipEventDestroy(s.done);
   }
   (void)hipFree(p->arena);
@@ -292,7 +299,6 @@ extern "C" int cc_pool_destroy(cc_pool* p) {
   (void)hipFree(p->flags);
   (void)hipFree(p->staging);
   (void)hipFree(p->check);
-  (void)hipFree(p->bar);
   (void)hipFree(p->table);
   delete p;
   return CC_OK;
@@ -465,7 +471,7 @@ extern "C" int cc_pool_run(cc_pool* p, const cc_op* ops, int32_t num_ops) {
   for (int32_t i = 0; i < num_ops; ++i) any_update |= ops[i].kind == 0 && ops[i].count > 0;
   const bool one_launch = p->tune.one_launch != 0;
   RingSlot* slot = nullptr;
-  int rc = reserve_slot(p, live, any_update && p->tune.compress_linked && !one_launch, &slot);
+  int rc = reserve_slot(p, live, any_update && p->tune.compress_linked && !one_launch, one_launch, &slot);
   if (rc != CC_OK) return rc;
   const int B = p->tune.block;
   // lay the descriptors out round by round; each round gets its own items per thread

@@ -322,6 +322,50 @@ def multi_graph_stream(g: int, n: int, edges_per_vertex=8, steps=4, qbatch=1 << 
                   _offsets([qbatch] * steps), meta=dict(kind=kind, graph=g))
 
 
+@dataclass
+class TraceRequest:
+    """One request of a serving trace: `items` are int32 [size, 2] edges
+    (kind 0, update) or pairs (kind 1, query) of graph `stream`."""
+    rid: int
+    stream: int
+    kind: int
+    size: int
+    items: np.ndarray
+
+
+def serving_trace(S=64, scale=22, R=1024, upd_frac=0.7, size_lo=8.0, size_hi=22.0,
+                  seed=BASE_SEED + 5) -> list:
+    """The serving workload: R requests over S graph streams, each graph an
+    R-MAT stream at `scale` (a=.57 b=.19 c=.19, ids permuted per graph).
+    Request i goes to a uniform stream; it is an update with probability
+    upd_frac, else a query; its size is floor(2^U), U ~ U[size_lo, size_hi].
+    An update takes the next `size` edges of its graph's stream, a query the
+    next `size` uniform pairs of the graph's query stream.  Arrival times are
+    drawn separately (poisson_arrivals with key P_ARRIVALS)."""
+    n = 1 << scale
+    kind_u = unit_doubles(key(seed, 0, P_REQ_TYPE), 0, R)
+    strm = np.minimum((unit_doubles(key(seed, 0, P_REQ_STREAM), 0, R) * S).astype(np.int64), S - 1)
+    sizes = np.floor(np.exp2(size_lo + (size_hi - size_lo) *
+                             unit_doubles(key(seed, 0, P_REQ_SIZE), 0, R))).astype(np.int64)
+    perms = {}
+    ecur = np.zeros(S, np.int64)
+    qcur = np.zeros(S, np.int64)
+    out = []
+    for i in range(R):
+        st, size = int(strm[i]), int(sizes[i])
+        if kind_u[i] < upd_frac:
+            if st not in perms:
+                perms[st] = permutation(key(seed, st + 1, P_PERM), n)
+            items = rmat_edges(key(seed, st + 1, P_EDGES), int(ecur[st]), size, scale, n, perms[st])
+            ecur[st] += size
+            out.append(TraceRequest(i, st, 0, size, items))
+        else:
+            items = uniform_pairs(key(seed, st + 1, P_QUERIES), int(qcur[st]), size, n)
+            qcur[st] += size
+            out.append(TraceRequest(i, st, 1, size, items))
+    return out
+
+
 def tiny_stream(n: int, edges, batches: list, queries=None) -> Stream:
     """A hand-written stream (tests)."""
     e = np.ascontiguousarray(np.asarray(edges, np.int32).reshape(-1, 2))

@@ -96,3 +96,85 @@ def test_capture_rejects_waiting_calls(cc):
         assert L.cc_capture_begin(g0.handle) == cc.cc.CC_EINVAL
     g0.close()
     g.close()
+
+
+@pytest.mark.parametrize("filt", [0, 2])
+def test_replay_after_eager_reset_keeps_forest_state(cc, filt):
+    """A recording that resets and updates, replayed after an eager reset,
+    leaves a forest with links: the linking order can no longer change, the
+    filter's bitmaps stay proofs, and answers and labels are the oracle's."""
+    import ctypes
+    s = synth.er_stream(n=1 << 12, batches=4, batch=1 << 11, qbatch=1 << 11, probes=0)
+    st = torch.cuda.Stream()
+    L = cc.lib()
+    with torch.cuda.stream(st):
+        E = torch.from_numpy(s.edges).cuda()
+        Q = torch.from_numpy(s.queries).cuda()
+        out = torch.zeros(len(s.queries), dtype=torch.uint8, device="cuda")
+        g = cc.Graph(s.n, stream=st, hook=2, compress_linked=0, filter=filt)
+        g.reserve(int(np.diff(s.eoff).max()))
+        with g.capture() as cap:
+            g.reset()
+            for i in range(2):
+                g.bulk_update(E[s.eoff[i]:s.eoff[i + 1]])
+        rec = cap.recording
+        g.reset()  # eager: the forest is pristine again
+        assert L.cc_set_option(g.handle, 6, 2) == 0  # same order: allowed
+        rec.launch()
+        st.synchronize()
+        # the replay linked vertices: another linking order is refused now
+        assert L.cc_set_option(g.handle, 6, 0) == cc.cc.CC_EINVAL
+        ref = oracle.UnionFind(s.n)
+        for i in range(2):
+            ref.bulk_update(s.batch(i))
+        for i in range(2, 4):
+            g.bulk_update(E[s.eoff[i]:s.eoff[i + 1]])
+            ref.bulk_update(s.batch(i))
+        got = g.bulk_query(Q[:4096], out=out[:4096])
+        st.synchronize()
+        np.testing.assert_array_equal(got.cpu().numpy(), ref.bulk_query(s.queries[:4096]))
+        np.testing.assert_array_equal(g.labels().cpu().numpy(), ref.labels())
+        assert g.num_components() == ref.num_components()
+        # after an eager reset the order may change, but this recording was
+        # made under union by rank and is refused under another order
+        g.reset()
+        assert L.cc_set_option(g.handle, 6, 0) == 0
+        assert L.cc_exec_launch(ctypes.c_void_p(rec._h)) == cc.cc.CC_EINVAL
+        assert g.sync() == cc.cc.CC_OK
+        rec.close()
+        g.close()
+
+
+def test_replay_of_recording_made_before_filter_bitmaps(cc):
+    """A recording made while the graph had no filter bitmaps resets and
+    updates the forest; bitmaps allocated later must not claim proofs about
+    the forest the replay leaves."""
+    s = synth.er_stream(n=1 << 12, batches=3, batch=1 << 11, qbatch=1 << 11, probes=0)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        E = torch.from_numpy(s.edges).cuda()
+        Q = torch.from_numpy(s.queries).cuda()
+        g = cc.Graph(s.n, stream=st, hook=2, compress_linked=0)
+        with g.capture() as cap:
+            g.reset()
+            g.bulk_update(E[s.eoff[0]:s.eoff[1]])
+        rec = cap.recording
+        # build filter state on another forest, then replay the old recording
+        g.set_option("filter", 2)
+        g.bulk_update(E[s.eoff[1]:s.eoff[3]])
+        g.bulk_query(Q[:1024])
+        rec.launch()
+        ref = oracle.UnionFind(s.n)
+        ref.bulk_update(s.batch(0))
+        got = g.bulk_query(Q)
+        st.synchronize()
+        np.testing.assert_array_equal(got.cpu().numpy(), ref.bulk_query(s.queries))
+        np.testing.assert_array_equal(g.labels().cpu().numpy(), ref.labels())
+        g.bulk_update(E[s.eoff[1]:s.eoff[2]])
+        ref.bulk_update(s.batch(1))
+        got = g.bulk_query(Q)
+        st.synchronize()
+        np.testing.assert_array_equal(got.cpu().numpy(), ref.bulk_query(s.queries))
+        assert g.sync() == cc.cc.CC_OK
+        rec.close()
+        g.close()

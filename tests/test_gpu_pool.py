@@ -226,3 +226,39 @@ def test_prepared_ops_rerun_with_new_contents(cc):
             np.testing.assert_array_equal(O[g].cpu().numpy(), refs[g], err_msg="run %d graph %d" % (run, g))
     assert pool.sync() == cc.cc.CC_OK
     pool.close()
+
+
+def test_overlapping_one_launch_runs_on_two_streams(cc):
+    """Runs of the one-launch form issued back to back on two streams (as the
+    serving executor does) each keep their own barrier and never run at the
+    same time; every answer equals the oracle's."""
+    G = 32
+    streams = small_graphs(G, seed=13)
+    half = G // 2
+    sts = [torch.cuda.Stream(), torch.cuda.Stream()]
+    pool = cc.Pool(sum(s.n for s in streams), G, one_launch=1, hook=2, compress_linked=0)
+    ids = [pool.add(s.n) for s in streams]
+    torch.cuda.synchronize()
+    outs = [torch.zeros(len(s.queries), dtype=torch.uint8, device="cuda") for s in streams]
+    E = [dev(s.edges) for s in streams]
+    Q = [dev(s.queries) for s in streams]
+    for k in range(4):
+        for part in range(2):
+            gs = range(part * half, (part + 1) * half)
+            ops = [(ids[g], cc.UPDATE, E[g][int(streams[g].eoff[k]):int(streams[g].eoff[k + 1])], None) for g in gs]
+            ops += [(ids[g], cc.QUERY, Q[g][int(streams[g].qoff[k]):int(streams[g].qoff[k + 1])],
+                     outs[g][int(streams[g].qoff[k]):int(streams[g].qoff[k + 1])]) for g in gs]
+            pool.set_stream(sts[part])
+            pool.run(ops)
+    torch.cuda.synchronize()
+    pool.set_stream(torch.cuda.current_stream())  # labels below are read on the current stream
+    for g, s in enumerate(streams):
+        ref = oracle.UnionFind(s.n)
+        want = []
+        for k in range(4):
+            ref.bulk_update(s.batch(k))
+            want.append(ref.bulk_query(s.query(k)))
+        np.testing.assert_array_equal(outs[g].cpu().numpy(), np.concatenate(want), err_msg="graph %d" % g)
+        np.testing.assert_array_equal(pool.labels(ids[g]).cpu().numpy(), ref.labels(), err_msg="graph %d" % g)
+    assert pool.sync() == cc.cc.CC_OK
+    pool.close()
