@@ -370,6 +370,11 @@ def run_grid(args):
             g.bulk_stream(E, eo, Q, qo, out, max_items=mx)
             g.labels(out=lab)
 
+        # the one-launch form takes its own launch shape (its grid is sized
+        # from the block and the largest minibatch)
+        stream_opts = tuning.lookup("stream", "grid", s.n)
+        for k, v in stream_opts.items():
+            g.set_option(k, v)
         out.zero_()
         wall_stream, c3 = timed(one_launch, args.steps, args.warmup, "stream-kernel")
         assert c1 == c3 and torch.equal(out, want), "stream kernel differs from plain launches"
@@ -381,7 +386,7 @@ def run_grid(args):
     res = result(steps * (M + Qn) / forms[best], args.steps, args.warmup, forms[best], {
         "workload": "grid4096-" + best, "n": s.n, "edges": M, "minibatches": nb, "minibatch": 1 << 12,
         "queries_per_minibatch": 1 << 10, "long_range_edges": s.meta["extra"], "form": best,
-        "options": opts})
+        "options": opts, "stream_kernel_options": stream_opts})
     res.update({"forms": {k: {"value": steps * (M + Qn) / v, "ms_per_step": v / steps * 1e3}
                           for k, v in forms.items()},
                 "speedup_vs_plain": wall_plain / forms[best], "components": c3})

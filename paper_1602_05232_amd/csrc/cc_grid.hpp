@@ -37,11 +37,16 @@ __device__ __forceinline__ unsigned bar_load(unsigned* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// FENCE = false: the same meeting point without the release and acquire
+// fences, for a phase boundary across which no data has to flow (the caller
+// states why); it still orders in time every access a block made before
+// arriving against every access made after the barrier releases.
+template <bool FENCE = true>
 __device__ __forceinline__ bool grid_sync(unsigned* bar, unsigned& gen, int* flags, unsigned spin_limit) {
   __shared__ int ok;
   __syncthreads();
   if (threadIdx.x == 0) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (FENCE) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     const unsigned target = gen + 1;
     int good = 1;
     const unsigned arrived = __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
@@ -50,8 +55,8 @@ __device__ __forceinline__ bool grid_sync(unsigned* bar, unsigned& gen, int* fla
       // synchronizes with every block's release fence (their increments are
       // in the release sequence it read), and its release store of the
       // generation with every waiter's acquire fence below.
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      __hip_atomic_store(bar + 32, target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      if (FENCE) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      __hip_atomic_store(bar + 32, target, FENCE ? __ATOMIC_RELEASE : __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
       unsigned spins = 0;
       while (bar_load(bar + 32) < target) {
@@ -73,7 +78,7 @@ __device__ __forceinline__ bool grid_sync(unsigned* bar, unsigned& gen, int* fla
     if (bar_load(bar + 64) != 0u) good = 0;
     ok = good;
     gen = target;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (FENCE) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
   return ok != 0;
