@@ -172,6 +172,23 @@ int cc_reset(cc_graph* g);
  * m exceeds the reserved size (see cc_reserve). */
 int cc_bulk_update(cc_graph* g, const int32_t* edges, int64_t m);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * Bulk-Update as cc_bulk_update, with the same results, that allocates
+ * nothing.  It always runs the fused schedule with linked-root compression,
+ * whatever CC_OPT_UPDATE_MODE, CC_OPT_FIND, CC_OPT_FILTER and
+ * CC_OPT_COMPRESS_LINKED say (any linking order; the filter's bitmaps, if
+ * they exist, are marked incomplete as after any unfiltered update).  Its
+ * scratch (the list of roots the call links and two counters) is a
+ * fixed-size array in the library's device code, one copy per device, held
+ * until the process ends; the call clears what must start at zero with a
+ * kernel, so it can be captured.  Limit: at most 2^22 edges per call
+ * (CC_EINVAL beyond, nothing enqueued).  Every call on a device shares that
+ * device's array: calls that overlap on one device (different streams,
+ * different graphs) race and must be ordered by the caller, e.g. on one
+ * stream. */
+int cc_bulk_update_noalloc(cc_graph* g, const int32_t* edges, int64_t m);
+
 /* Bulk-Query (Algorithm 1, Simple-Bulk-Query): out[i] = 1 if pairs[i] are
  * connected by the edges of all earlier updates on g, else 0.  pairs is
  * device int32[q][2], out is device uint8[q], written in input order.  A pair

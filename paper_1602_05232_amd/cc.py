@@ -36,6 +36,7 @@ SIGNATURES = {
     "cc_reserve": (_i32, [_vp, _i64]),
     "cc_reset": (_i32, [_vp]),
     "cc_bulk_update": (_i32, [_vp, _vp, _i64]),
+    "cc_bulk_update_noalloc": (_i32, [_vp, _vp, _i64]),
     "cc_bulk_query": (_i32, [_vp, _vp, _i64, _vp]),
     "cc_bulk_stream": (_i32, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _i64]),
     "cc_labels": (_i32, [_vp, _vp]),
@@ -209,6 +210,12 @@ class Graph:
     def bulk_update(self, edges: torch.Tensor):
         p = _pairs_ptr(edges, "edges")
         _check(lib().cc_bulk_update(self._h, p, edges.shape[0] if edges.numel() else 0))
+
+    def bulk_update_noalloc(self, edges: torch.Tensor):
+        """Bulk-Update through cc_bulk_update_noalloc (no device allocation;
+        at most 2^22 edges per call)."""
+        p = _pairs_ptr(edges, "edges")
+        _check(lib().cc_bulk_update_noalloc(self._h, p, edges.shape[0] if edges.numel() else 0))
 
     def bulk_query(self, pairs: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         p = _pairs_ptr(pairs, "pairs")

@@ -84,6 +84,11 @@ extern "C" const char* cc_strerror(int code) {
   }
 }
 
+// Scratch of cc_bulk_update_noalloc (layout and use at noalloc_scratch).
+constexpr int64_t kNoAllocMaxEdges = int64_t(1) << 22;
+constexpr int kNoAllocHeadWords = 64;
+static __device__ __align__(256) int32_t scratch[kNoAllocHeadWords + kNoAllocMaxEdges];
+
 struct cc_graph {
   int64_t n = 0;
   int device = 0;
@@ -255,47 +260,50 @@ int launch_init(cc_graph* g) {
   return CC_OK;
 }
 
+// The fused update; with RECORD the roots it links go to `hooked`, counted in
+// hooked_ctl[0] (hooked_ctl[1]: completion counter of the compress pass).
 template <int ITEMS, class Ord, bool RECORD, bool FILT>
-void launch_fused_t(cc_graph* g, const int2* e, int64_t m) {
+void launch_fused_t(cc_graph* g, const int2* e, int64_t m, int32_t* hooked, unsigned* hooked_ctl) {
   const int B = g->tune.block;
   const unsigned blocks = blocks_for(m, (int64_t)B * ITEMS, g->tune.grid_cap);
   hipLaunchKernelGGL((k_update_fused<ITEMS, Ord, RECORD, FILT>), dim3(blocks), dim3(B), 0, g->stream, g->parent,
-                     e, m, (int32_t)g->n, g->slots, g->flags, g->hooked, g->live_ctl + 2, g->member_ctl,
-                     g->member);
+                     e, m, (int32_t)g->n, g->slots, g->flags, hooked, hooked_ctl, g->member_ctl, g->member);
 }
 
 template <class Ord, bool RECORD, bool FILT>
-void launch_fused_f(cc_graph* g, const int2* e, int64_t m) {
+void launch_fused_f(cc_graph* g, const int2* e, int64_t m, int32_t* hooked, unsigned* hooked_ctl) {
   int items = cc::pick_items(g->tune.items, m, g->tune.block);
   while (FILT && items > 1 && g->tune.block * items > kDeferTileMax) items >>= 1;  // a tile fits the list
   switch (items) {
-    case 1: launch_fused_t<1, Ord, RECORD, FILT>(g, e, m); break;
-    case 2: launch_fused_t<2, Ord, RECORD, FILT>(g, e, m); break;
-    case 8: launch_fused_t<8, Ord, RECORD, FILT>(g, e, m); break;
-    default: launch_fused_t<4, Ord, RECORD, FILT>(g, e, m); break;
+    case 1: launch_fused_t<1, Ord, RECORD, FILT>(g, e, m, hooked, hooked_ctl); break;
+    case 2: launch_fused_t<2, Ord, RECORD, FILT>(g, e, m, hooked, hooked_ctl); break;
+    case 8: launch_fused_t<8, Ord, RECORD, FILT>(g, e, m, hooked, hooked_ctl); break;
+    default: launch_fused_t<4, Ord, RECORD, FILT>(g, e, m, hooked, hooked_ctl); break;
   }
 }
 
 template <class Ord, bool RECORD>
-void launch_fused_r(cc_graph* g, const int2* e, int64_t m) {
+void launch_fused_r(cc_graph* g, const int2* e, int64_t m, int32_t* hooked, unsigned* hooked_ctl) {
   if (g->tune.filter && g->member) {
     member_pick<is_ranked<Ord>::value>(g, e, m);
-    launch_fused_f<Ord, RECORD, true>(g, e, m);
+    launch_fused_f<Ord, RECORD, true>(g, e, m, hooked, hooked_ctl);
   } else {
     member_touched_invalid(g);
-    launch_fused_f<Ord, RECORD, false>(g, e, m);
+    launch_fused_f<Ord, RECORD, false>(g, e, m, hooked, hooked_ctl);
   }
 }
 
+// Fused update, then (with linked-root compression) the compress pass over
+// the roots it linked.
 template <class Ord>
 void launch_fused_o(cc_graph* g, const int2* e, int64_t m) {
   if (g->tune.compress_linked) {
-    launch_fused_r<Ord, true>(g, e, m);
+    launch_fused_r<Ord, true>(g, e, m, g->hooked, g->live_ctl + 2);
     const unsigned blocks = blocks_for(std::min<int64_t>(m, g->n), 256, 1024);
     hipLaunchKernelGGL(k_compress_hooked<is_ranked<Ord>::value>, dim3(blocks), dim3(256), 0, g->stream,
                        g->parent, g->hooked, g->live_ctl + 2, (int32_t)g->n, g->flags);
   } else {
-    launch_fused_r<Ord, false>(g, e, m);
+    launch_fused_r<Ord, false>(g, e, m, nullptr, nullptr);
   }
 }
 
@@ -461,6 +469,64 @@ int launch_bulk_find(cc_graph* g, const int2* items, int64_t count, uint8_t* out
   if (g->tune.hook == 1) return launch_bulk_find_t<KIND, ByHash>(g, items, count, out);
   if (g->tune.hook == 2) return launch_bulk_find_t<KIND, ByRank>(g, items, count, out);
   return launch_bulk_find_t<KIND, ById>(g, items, count, out);
+}
+
+// Host state after an update call, and the periodic full compression.
+void after_update(cc_graph* g) {
+  g->updates++;
+  g->pristine = false;
+  if (g->capturing) g->cap_updates++;
+  if (g->tune.compress_every > 0 && g->updates % g->tune.compress_every == 0) {
+    if (g->tune.hook == 2)
+      hipLaunchKernelGGL(k_compress_all<true>, dim3(vertex_blocks(g)), dim3(256), 0, g->stream, g->parent,
+                         (int32_t)g->n, g->flags);
+    else
+      hipLaunchKernelGGL(k_compress_all<false>, dim3(vertex_blocks(g)), dim3(256), 0, g->stream, g->parent,
+                         (int32_t)g->n, g->flags);
+  }
+}
+
+// Scratch of cc_bulk_update_noalloc: words [0, 64) hold the count of the
+// linked-root list and the completion counter of the compress pass (one
+// 256-byte line), words [64, 64 + kNoAllocMaxEdges) hold the list (at most
+// one linked root per edge).  Every device the library runs on holds its own
+// copy until the process ends.  Host code never uses the array's name as an
+// address: it asks the runtime for each device's address once
+// (noalloc_scratch) and passes that.
+constexpr int kNoAllocDevices = 64;
+std::mutex g_scratch_mu;
+int32_t* g_scratch_ptr[kNoAllocDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the
+// first call on each device).
+int noalloc_scratch(int32_t** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kNoAllocDevices) {
+    cc_set_error("cc_bulk_update_noalloc: device %d beyond the %d the library keeps scratch addresses for", dev,
+                 kNoAllocDevices);
+    return CC_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[dev] = static_cast<int32_t*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return CC_OK;
+}
+
+template <class Ord>
+void launch_fused_noalloc(cc_graph* g, const int2* e, int64_t m, int32_t* sc) {
+  unsigned* ctl = reinterpret_cast<unsigned*>(sc);
+  int32_t* list = sc + kNoAllocHeadWords;
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, g->stream, ctl, 2);  // a kernel, not a memset node
+  member_touched_invalid(g);
+  launch_fused_f<Ord, true, false>(g, e, m, list, ctl);
+  const unsigned blocks = blocks_for(std::min<int64_t>(m, g->n), 256, 1024);
+  hipLaunchKernelGGL(k_compress_hooked<is_ranked<Ord>::value>, dim3(blocks), dim3(256), 0, g->stream, g->parent,
+                     list, ctl, (int32_t)g->n, g->flags);
 }
 
 }  // namespace
@@ -665,17 +731,31 @@ extern "C" int cc_bulk_update(cc_graph* g, const int32_t* edges, int64_t m) {
     else if (hashed) launch_fused_o<ByHash>(g, e, m);
     else launch_fused_o<ById>(g, e, m);
   }
-  g->updates++;
-  g->pristine = false;
-  if (g->capturing) g->cap_updates++;
-  if (g->tune.compress_every > 0 && g->updates % g->tune.compress_every == 0) {
-    if (ranked)
-      hipLaunchKernelGGL(k_compress_all<true>, dim3(vertex_blocks(g)), dim3(256), 0, g->stream, g->parent,
-                         (int32_t)g->n, g->flags);
-    else
-      hipLaunchKernelGGL(k_compress_all<false>, dim3(vertex_blocks(g)), dim3(256), 0, g->stream, g->parent,
-                         (int32_t)g->n, g->flags);
+  after_update(g);
+  HIP_TRY(hipGetLastError());
+  return CC_OK;
+}
+
+extern "C" int cc_bulk_update_noalloc(cc_graph* g, const int32_t* edges, int64_t m) {
+  if (!g || m < 0 || (m > 0 && (!edges || cc::misaligned8(edges)))) {
+    cc_set_error("cc_bulk_update_noalloc: invalid argument (edges must be 8-byte aligned device memory)");
+    return CC_EINVAL;
   }
+  if (m > kNoAllocMaxEdges) {
+    cc_set_error("cc_bulk_update_noalloc: %lld edges exceed the limit of %lld per call", (long long)m,
+                 (long long)kNoAllocMaxEdges);
+    return CC_EINVAL;
+  }
+  if (m == 0) return CC_OK;
+  DeviceGuard dg(g->device);
+  int32_t* sc = nullptr;
+  int rc = noalloc_scratch(&sc);
+  if (rc != CC_OK) return rc;
+  const int2* e = reinterpret_cast<const int2*>(edges);
+  if (g->tune.hook == 2) launch_fused_noalloc<ByRank>(g, e, m, sc);
+  else if (g->tune.hook == 1) launch_fused_noalloc<ByHash>(g, e, m, sc);
+  else launch_fused_noalloc<ById>(g, e, m, sc);
+  after_update(g);
   HIP_TRY(hipGetLastError());
   return CC_OK;
 }
