@@ -233,6 +233,9 @@ def run_rmat(args):
     rc = g.sync()
     if rc != 0:
         raise SystemExit("device reported status %d" % rc)
+    for ev in ev_sets:  # released here, not at interpreter shutdown
+        for e in ev:
+            e.close()
     steps = max(1, args.steps)
     upd_rate = steps * M / sum(upd_t)
     qry_rate = steps * Qn / sum(qry_t)
@@ -297,10 +300,130 @@ def run_rmat(args):
                         "a query pair reads one to four words"}
             log("filter roofline: G(bitmap)=%.3g/s E_f=%.3g e/s (frac %.3f) Q_f=%.3g q/s (frac %.3f)"
                 % (Gb, Ef, upd_rate / Ef, Qf, qry_rate / Qf))
+        # which measured ceiling binds this path: a fraction above 1 means the
+        # path does not do the work that denominator prices (the filter turns
+        # parent gathers into bitmap hits), so that ceiling does not bind it
+        gr = res["gather_roofline"]
+        cands = {"E_roof (two parent gathers from a table of n + 8 streamed bytes per edge)":
+                 (gr["E_roof_edges_per_s"], gr["frac"], gr["query_roof_per_s"], gr["query_frac"])}
+        if "filter" in gr:
+            f = gr["filter"]
+            cands["E_f (two bitmap gathers + 8 streamed bytes per item)"] = (
+                f["E_filter_roof_edges_per_s"], f["update_frac_of_filter_roof"], f["Q_filter_roof_per_s"],
+                f["query_frac_of_filter_roof"])
+        binding = {k: v for k, v in cands.items() if v[1] <= 1.0 and v[3] <= 1.0}
+        name = min(binding, key=lambda k: binding[k][0]) if binding else None
+        res["roofline"]["binding_ceiling"] = None if name is None else {
+            "name": name, "update_edges_per_s": binding[name][0], "update_frac": binding[name][1],
+            "query_pairs_per_s": binding[name][2], "query_frac": binding[name][3]}
+        res["roofline"]["non_binding"] = {k: {"update_frac": v[1], "query_frac": v[3]}
+                                          for k, v in cands.items() if k != name}
     g.close()
+    if opts.get("filter", 0) and not args.no_forms:
+        res["unfiltered"] = rmat_unfiltered(s, opts, max(2, min(args.steps, 5)))
+        log("unfiltered: update %.3g edges/s, query %.3g pairs/s" % (
+            res["unfiltered"]["update_edges_per_s"], res["unfiltered"]["queries_per_s"]))
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline([s], args.cpu_budget)
         log("cpu baseline: %s" % res["cpu_baseline"]["sample"])
+    return res
+
+
+def rmat_unfiltered(s, opts, steps):
+    """The same stream without the membership filter (union by rank, the
+    unfiltered path's own launch shape): every edge and pair takes its two
+    parent gathers, the work E_roof prices."""
+    import torch
+
+    import paper_1602_05232_amd as ccgpu
+    from paper_1602_05232_amd import roofline, tuning
+
+    uo = dict(opts)
+    uo.update(tuning.lookup("plain", "rmat-unfiltered", s.n) or dict(filter=0, block=1024, items=0, grid_cap=4096))
+    uo["filter"] = 0
+    E = torch.from_numpy(s.edges).cuda()
+    Q = torch.from_numpy(s.queries).cuda()
+    out = torch.empty(len(s.queries), dtype=torch.uint8, device="cuda")
+    nb = s.num_batches
+    Es = [E[int(s.eoff[i]):int(s.eoff[i + 1])] for i in range(nb)]
+    Qs = [Q[int(s.qoff[i]):int(s.qoff[i + 1])] for i in range(nb)]
+    Os = [out[int(s.qoff[i]):int(s.qoff[i + 1])] for i in range(nb)]
+    g = ccgpu.Graph(s.n, **uo)
+    stream = torch.cuda.current_stream()
+    ev = [roofline.TimingEvent() for _ in range(2 * nb + 1)]
+    tu, tq = [], []
+    for k in range(steps + 1):
+        g.reset()
+        for i in range(nb):
+            ev[2 * i].record(stream)
+            g.bulk_update(Es[i])
+            ev[2 * i + 1].record(stream)
+            g.bulk_query(Qs[i], out=Os[i])
+        ev[2 * nb].record(stream)
+        torch.cuda.synchronize()
+        if k > 0:  # the first pass warms up
+            tu.append(sum(ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(nb)) / 1e3)
+            tq.append(sum(ev[2 * i + 1].elapsed_time(ev[2 * i + 2]) for i in range(nb)) / 1e3)
+    assert g.sync() == 0
+    g.close()
+    for e in ev:
+        e.close()
+    M, Qn = len(s.edges), len(s.queries)
+    return {"update_edges_per_s": M * len(tu) / sum(tu), "queries_per_s": Qn * len(tq) / sum(tq),
+            "update_ms_per_pass": sum(tu) / len(tu) * 1e3, "query_ms_per_pass": sum(tq) / len(tq) * 1e3,
+            "options": uo, "steps": len(tu)}
+
+
+def run_er(args):
+    """The tiny uniform stream: n = 2^16, 16 minibatches of 2^14 uniform edges
+    (self-loops and repeats kept), each followed by 2^14 uniform query pairs;
+    plain launches.  Launch-latency bound: a pass is 32 operations of
+    2^14 items."""
+    import torch
+
+    import synth
+    import paper_1602_05232_amd as ccgpu
+    from paper_1602_05232_amd import tuning
+
+    s = synth.er_stream()
+    M, Qn, nb = len(s.edges), len(s.queries), s.num_batches
+    opts = tuning.plain_options(s.n, workload="er")
+    if args.options:
+        opts.update(parse_options(args.options))
+    E = torch.from_numpy(s.edges).cuda()
+    Q = torch.from_numpy(s.queries).cuda()
+    out = torch.empty(Qn, dtype=torch.uint8, device="cuda")
+    lab = torch.empty(s.n, dtype=torch.int32, device="cuda")
+    g = ccgpu.Graph(s.n, **opts)
+    g.reserve(int(s.eoff[1] - s.eoff[0]))
+    Es = [E[int(s.eoff[i]):int(s.eoff[i + 1])] for i in range(nb)]
+    Qs = [Q[int(s.qoff[i]):int(s.qoff[i + 1])] for i in range(nb)]
+    Os = [out[int(s.qoff[i]):int(s.qoff[i + 1])] for i in range(nb)]
+
+    def step():
+        g.reset()
+        for i in range(nb):
+            g.bulk_update(Es[i])
+            g.bulk_query(Qs[i], out=Os[i])
+        g.labels(out=lab)
+        return g.num_components()
+
+    for _ in range(max(1, args.warmup)):
+        c = step()
+    steps = max(5, args.steps)
+    times = []
+    for _ in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c = step()
+        times.append(time.perf_counter() - t0)
+    assert g.sync() == 0
+    g.close()
+    med = sorted(times)[len(times) // 2]
+    res = result((M + Qn) / med, steps, args.warmup, sum(times), {
+        "workload": "er16-plain", "n": s.n, "edges": M, "minibatches": nb, "minibatch": 1 << 14,
+        "queries_per_minibatch": 1 << 14, "form": "plain", "options": opts})
+    res.update({"median_ms_per_pass": med * 1e3, "components": c})
     return res
 
 
@@ -587,22 +710,38 @@ def run_serve(args):
 
     zeros = np.zeros(R)
     full = S * n
+    reps = max(3, args.steps)
+
+    def median_run(form, times, budget):
+        """reps runs of one form; the run with the median wall time, plus
+        the medians of its latency figures over the runs."""
+        runs = [run(form, times, budget) for _ in range(reps)]
+        runs.sort(key=lambda r: r[0]["wall_s"])
+        info, answers = runs[len(runs) // 2]
+        info = dict(info)
+        for key in ("p50_ms", "p99_ms"):
+            if key in info:
+                info[key] = float(np.median([r[0][key] for r in runs]))
+        info["runs"] = len(runs)
+        info["wall_s_all"] = [r[0]["wall_s"] for r in runs]
+        return info, answers
+
     for _ in range(args.warmup):
         run("served", zeros, full)
-    sat_served, a1 = run("served", zeros, full)
-    sat_serial, a2 = run("serial", zeros, full)
+    sat_served, a1 = median_run("served", zeros, full)
+    sat_serial, a2 = median_run("serial", zeros, full)
     for rid in a1:
         assert torch.equal(a1[rid], a2[rid]), "served and serial answers differ"
     # latency at 70% of the serial form's capacity (requests per second)
     lam = 0.7 * R / sat_serial["wall_s"]
     arr = synth.poisson_arrivals(synth.key(seed, 0, synth.P_ARRIVALS), R, lam)
-    lat_served, _ = run("served", arr, full)
-    lat_serial, _ = run("serial", arr, full)
+    lat_served, _ = median_run("served", arr, full)
+    lat_serial, _ = median_run("serial", arr, full)
     budget = (256 << 20) // 4  # 256 MiB of parent entries: a quarter of the graphs resident
     lat_evict, a3 = run("served", arr, budget)
     for rid in a1:
         assert torch.equal(a1[rid], a3[rid]), "answers changed under eviction"
-    res = result((tot_e + tot_q) / sat_served["wall_s"], 1, args.warmup, sat_served["wall_s"], {
+    res = result((tot_e + tot_q) / sat_served["wall_s"], reps, args.warmup, sat_served["wall_s"] * reps, {
         "workload": "serve%d-rmat%d" % (S, scale), "streams": S, "n_per_stream": n, "requests": R,
         "update_fraction": 0.7, "request_sizes": "floor(2^U), U ~ U[8, 22]", "update_edges": tot_e,
         "query_pairs": tot_q, "form": "served (continuous batching, 2 HIP streams)", "options": popts})
@@ -737,13 +876,51 @@ def run_components(args):
     return res
 
 
+def compact(r: dict, keys) -> dict:
+    out = {"value": r["value"], "unit": r["unit"], "ms_per_step": r["ms_per_step"]}
+    for k in keys:
+        if k in r:
+            out[k] = r[k]
+    return out
+
+
+def run_forms(args) -> dict:
+    """Every workload's forms against its plain form, each on its own
+    configuration (a few steps each, medians where a form is short)."""
+    import copy
+    import torch
+
+    sub = copy.copy(args)
+    sub.steps, sub.warmup, sub.no_cpu_baseline, sub.options = max(3, min(args.steps, 5)), 1, True, ""
+    forms = {}
+    r = run_er(sub)
+    forms["er16"] = compact(r, ("median_ms_per_pass", "components", "config"))
+    log("forms: er16 %.3g items/s" % r["value"])
+    torch.cuda.empty_cache()
+    r = run_grid(sub)
+    forms["grid4096"] = compact(r, ("forms", "speedup_vs_plain", "components", "config"))
+    log("forms: grid4096 %s" % {k: "%.1f ms" % v["ms_per_step"] for k, v in r["forms"].items()})
+    torch.cuda.empty_cache()
+    r = run_batched(sub)
+    forms["batched1024"] = compact(r, ("plain_value", "plain_ms_per_step", "plain_options", "speedup_vs_plain",
+                                       "one_launch", "components", "config"))
+    log("forms: batched1024 pool %.1f ms, per-graph %.1f ms" % (r["ms_per_step"], r["plain_ms_per_step"]))
+    torch.cuda.empty_cache()
+    r = run_serve(sub)
+    forms["serve64"] = compact(r, ("saturation", "poisson_rate_per_s", "latency_at_0.7_serial_capacity",
+                                   "latency_with_256MiB_budget", "config"))
+    log("forms: serve64 served/serial saturation speedup %.2f" % r["saturation"]["speedup"])
+    torch.cuda.empty_cache()
+    return forms
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat24",
-                    choices=["rmat24", "grid4096", "batched1024", "serve64", "bigbatch", "components"])
+                    choices=["rmat24", "er16", "grid4096", "batched1024", "serve64", "bigbatch", "components"])
     ap.add_argument("--requests", type=int, default=1024, help="requests of the serving trace")
     ap.add_argument("--serve-scale", type=int, default=22, help="R-MAT scale of each served graph")
     ap.add_argument("--scale", type=int, default=24, help="R-MAT scale of the rmat24 workload")
@@ -753,6 +930,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="rmat24 only: skip the other workloads' forms (plain vs batched vs served)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -765,8 +944,10 @@ def main():
     if not os.path.exists(hipbuild.OUT):
         import __graft_entry__
         __graft_entry__.build()
-    res = {"rmat24": run_rmat, "grid4096": run_grid, "batched1024": run_batched,
+    res = {"rmat24": run_rmat, "er16": run_er, "grid4096": run_grid, "batched1024": run_batched,
            "serve64": run_serve, "bigbatch": run_bigbatch, "components": run_components}[args.workload](args)
+    if args.workload == "rmat24" and not args.no_forms:
+        res["forms"] = run_forms(args)
     print(json.dumps(res), flush=True)
 
 

@@ -88,10 +88,18 @@ class TimingEvent:
             raise RuntimeError("ccb_event_elapsed_ms failed (%d)" % rc)
         return ms.value
 
-    def __del__(self):
+    def close(self):
+        """Release the event now (before interpreter shutdown, when the
+        runtime may already be tearing down)."""
         h, self.handle = getattr(self, "handle", None), None
         if h:
             lib().ccb_event_destroy(h)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def copy_bytes(dst: torch.Tensor, src: torch.Tensor, nbytes: int):
