@@ -496,6 +496,7 @@ def run_grid(args):
         # the one-launch form takes its own launch shape (its grid is sized
         # from the block and the largest minibatch)
         stream_opts = tuning.lookup("stream", "grid", s.n)
+        g.reset()  # a fresh forest may change its linking order
         for k, v in stream_opts.items():
             g.set_option(k, v)
         out.zero_()
@@ -680,7 +681,7 @@ def run_serve(args):
     torch.cuda.synchronize()
     log("serving trace: %d requests over %d streams of n=2^%d, %d update edges, %d query pairs (%.1fs)"
         % (R, S, scale, tot_e, tot_q, time.perf_counter() - t))
-    popts = tuning.lookup("pool", "mixed", n) or {}
+    popts = tuning.lookup("serve", "rmat", n) or tuning.lookup("pool", "mixed", n) or {}
     popts = {k: v for k, v in popts.items() if k not in ("update_mode", "compress_every")}
     popts["compress_linked"] = 0  # rounds overlap on two streams
 

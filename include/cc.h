@@ -69,7 +69,7 @@ enum cc_option {
    * in the minibatch; the open question of Section 7 about very large
    * minibatches).  Id and hashed orders only, not available during capture,
    * at most 2^31 - 1 edges per call.
-   * Union by rank (CC_OPT_HOOK 2) takes schedule 0 only.  Default 0. */
+   * Union by rank (CC_OPT_HOOK 2) takes schedules 0 and 1.  Default 0. */
   CC_OPT_UPDATE_MODE = 1,
   CC_OPT_BLOCK = 2,          /* threads per block, multiple of 64 in [64, 1024]; default 256 */
   CC_OPT_ITEMS = 3,          /* edges (or pairs) per thread: 1, 2, 4 or 8, or 0 = chosen per
@@ -131,7 +131,20 @@ enum cc_option {
   /* Pairs per thread of Bulk-Query: 1, 2, 4 or 8, or 0 = as CC_OPT_ITEMS
    * (default), for when queries and updates want different amounts of work
    * in flight per thread. */
-  CC_OPT_QUERY_ITEMS = 13
+  CC_OPT_QUERY_ITEMS = 13,
+  /* Compaction threshold of the fused schedule (CC_OPT_UPDATE_MODE 0), a
+   * percentage in [0, 100].  t > 0: an update whose minibatch is expected to
+   * keep fewer than t% of its edges live (edges whose endpoints' roots
+   * differ, the contracted edge list A'' of Algorithm 2) runs the split
+   * schedule, which compacts the live edges before linking them; the others
+   * run fused.  The estimate is the fraction of edges that linked in the
+   * latest earlier updates whose link counts have reached the host: after
+   * each such update the library copies its link counters to pinned host
+   * memory asynchronously and reads them at a later call once the copy has
+   * finished, so no call waits for the device.  The first update after
+   * creation or a reset runs fused.  During capture the schedule of the last
+   * eager decision is recorded.  0 = always fused (default). */
+  CC_OPT_SPLIT_BELOW = 14
 };
 
 /* Create a graph on vertices [0, n), 1 <= n <= 2^31 - 1, every vertex its own

@@ -18,12 +18,12 @@ LIB_PATH = os.path.join(_HERE, "libcc.so")
 CC_OK, CC_EINVAL, CC_ENOMEM, CC_ERANGE, CC_EDEVICE, CC_ECORRUPT = 0, -1, -2, -3, -4, -5
 OPT_UPDATE_MODE, OPT_BLOCK, OPT_ITEMS, OPT_QUERY_HALVING = 1, 2, 3, 4
 OPT_COMPRESS_EVERY, OPT_HOOK, OPT_GRID_CAP, OPT_COMPRESS_LINKED, OPT_SPIN_LIMIT, OPT_FIND = 5, 6, 7, 8, 9, 10
-OPT_ONE_LAUNCH, OPT_FILTER, OPT_QUERY_ITEMS = 11, 12, 13
+OPT_ONE_LAUNCH, OPT_FILTER, OPT_QUERY_ITEMS, OPT_SPLIT_BELOW = 11, 12, 13, 14
 _OPT_NAMES = {"update_mode": OPT_UPDATE_MODE, "block": OPT_BLOCK, "items": OPT_ITEMS,
               "query_halving": OPT_QUERY_HALVING, "compress_every": OPT_COMPRESS_EVERY,
               "hook": OPT_HOOK, "grid_cap": OPT_GRID_CAP, "compress_linked": OPT_COMPRESS_LINKED,
               "spin_limit": OPT_SPIN_LIMIT, "find": OPT_FIND, "one_launch": OPT_ONE_LAUNCH,
-              "filter": OPT_FILTER, "query_items": OPT_QUERY_ITEMS}
+              "filter": OPT_FILTER, "query_items": OPT_QUERY_ITEMS, "split_below": OPT_SPLIT_BELOW}
 
 # Every symbol include/cc.h declares, with (restype, argtypes).
 _vp, _i64, _i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int

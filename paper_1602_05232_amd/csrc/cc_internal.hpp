@@ -59,6 +59,7 @@ struct Tuning {
   int one_launch = 0;            // CC_OPT_ONE_LAUNCH (pools)
   int filter = 0;                // CC_OPT_FILTER
   int query_items = 0;           // CC_OPT_QUERY_ITEMS (0 = as CC_OPT_ITEMS)
+  int split_below = 0;           // CC_OPT_SPLIT_BELOW (percent; 0 = always fused)
 };
 
 inline bool set_tuning(Tuning* t, int key, int64_t v) {
@@ -115,6 +116,10 @@ inline bool set_tuning(Tuning* t, int key, int64_t v) {
       if (v != 0 && v != 1 && v != 2 && v != 4 && v != 8) return false;
       t->query_items = (int)v;
       return true;
+    case CC_OPT_SPLIT_BELOW:
+      if (v < 0 || v > 100) return false;
+      t->split_below = (int)v;
+      return true;
     default:
       return false;
   }
@@ -135,6 +140,7 @@ inline bool get_tuning(const Tuning* t, int key, int64_t* v) {
     case CC_OPT_ONE_LAUNCH: *v = t->one_launch; return true;
     case CC_OPT_FILTER: *v = t->filter; return true;
     case CC_OPT_QUERY_ITEMS: *v = t->query_items; return true;
+    case CC_OPT_SPLIT_BELOW: *v = t->split_below; return true;
     default: return false;
   }
 }

@@ -276,8 +276,9 @@ __global__ void k_update_fused(int32_t* __restrict__ parent, const int2* __restr
   count_links(slots, links);
 }
 
-// Relabel + filter + compact.  live_ctl[0] is the live count.
-template <int ITEMS>
+// Relabel + filter + compact.  live_ctl[0] is the live count.  R: root
+// words carry rank bits (union by rank).
+template <int ITEMS, bool R>
 __global__ void k_filter(int32_t* __restrict__ parent, const int2* __restrict__ edges, int64_t m, int32_t n,
                          int2* __restrict__ live, unsigned* __restrict__ live_ctl, int* __restrict__ flags) {
   extern __shared__ int2 stage[];  // blockDim.x * ITEMS pairs
@@ -298,7 +299,7 @@ __global__ void k_filter(int32_t* __restrict__ parent, const int2* __restrict__ 
         e = make_int2(0, 0);
       }
       r[k] = e.x == e.y ? make_int2(0, 0)
-                        : make_int2(find_halve(parent, e.x, n, flags), find_halve(parent, e.y, n, flags));
+                        : make_int2(find_halve<R>(parent, e.x, n, flags), find_halve<R>(parent, e.y, n, flags));
       cnt += r[k].x != r[k].y;
     }
     // exclusive scan of cnt over the wavefront
@@ -342,7 +343,7 @@ __global__ void k_link_live(int32_t* __restrict__ parent, const int2* __restrict
   int links = 0;
   for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < L; i += gridDim.x * blockDim.x) {
     const int2 p = live[i];
-    links += link_roots(parent, p.x, p.y, n, flags, Ord{}) >= 0;
+    links += link(parent, p.x, p.y, n, flags, Ord{}) >= 0;
   }
   count_links(slots, links);
 }
@@ -365,13 +366,14 @@ __device__ __forceinline__ void compress_path(int32_t* parent, int32_t x, int32_
 // Compress the paths of both live roots.  The last block to finish clears the
 // live count (live_ctl[0]) and its own completion counter (live_ctl[1]), so
 // the next minibatch starts from an empty list without a host call.
+template <bool R = false>
 __global__ void k_compress_live(int32_t* __restrict__ parent, const int2* __restrict__ live,
                                 unsigned* __restrict__ live_ctl, int32_t n, int* __restrict__ flags) {
   const unsigned L = __hip_atomic_load(live_ctl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < L; i += gridDim.x * blockDim.x) {
     const int2 p = live[i];
-    compress_path(parent, p.x, n, flags);
-    compress_path(parent, p.y, n, flags);
+    compress_path<R>(parent, p.x, n, flags);
+    compress_path<R>(parent, p.y, n, flags);
   }
   __syncthreads();
   if (threadIdx.x == 0) {

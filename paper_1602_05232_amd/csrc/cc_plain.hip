@@ -113,6 +113,22 @@ struct cc_graph {
   int64_t live_cap = 0;
   int64_t updates = 0;
   bool capturing = false;
+  // compaction threshold (CC_OPT_SPLIT_BELOW): link-counter snapshots copied
+  // to pinned host memory after updates, read once their copies finished
+  struct Snap {
+    unsigned long long* host = nullptr;  // kSlots * kSlotStride words, pinned
+    hipEvent_t done = nullptr;
+    bool pending = false;
+    int64_t epoch = 0;    // reset count when taken
+    int64_t edges = 0;    // edges of all updates since the reset, up to this one
+  } snap[2];
+  int snap_next = 0;
+  int64_t epoch = 0;          // cc_reset / cc_load count
+  int64_t epoch_edges = 0;    // edges since the last reset
+  int64_t base_links = 0, base_edges = 0;  // the last snapshot read, in this epoch
+  bool base_valid = true;     // base_links / base_edges describe the same moment
+  double live_est = 1.0;      // estimated live fraction (links per edge) of recent updates
+  bool split_now = false;     // the schedule chosen by the last eager decision
   // effect of the calls recorded so far in the current capture on the
   // forest: a reset was recorded; updates recorded since the last reset (or
   // since the capture began)
@@ -307,27 +323,28 @@ void launch_fused_o(cc_graph* g, const int2* e, int64_t m) {
   }
 }
 
-template <int ITEMS>
+template <int ITEMS, bool R>
 void launch_filter_t(cc_graph* g, const int2* e, int64_t m) {
   const int B = g->tune.block;
   const unsigned blocks = blocks_for(m, (int64_t)B * ITEMS, g->tune.grid_cap);
-  hipLaunchKernelGGL((k_filter<ITEMS>), dim3(blocks), dim3(B), (size_t)B * ITEMS * sizeof(int2), g->stream,
+  hipLaunchKernelGGL((k_filter<ITEMS, R>), dim3(blocks), dim3(B), (size_t)B * ITEMS * sizeof(int2), g->stream,
                      g->parent, e, m, (int32_t)g->n, g->live, g->live_ctl, g->flags);
 }
 
 template <class Ord>
 void launch_split_o(cc_graph* g, const int2* e, int64_t m) {
+  constexpr bool R = is_ranked<Ord>::value;
   switch (cc::pick_items(g->tune.items, m, g->tune.block)) {
-    case 1: launch_filter_t<1>(g, e, m); break;
-    case 2: launch_filter_t<2>(g, e, m); break;
-    case 8: launch_filter_t<8>(g, e, m); break;
-    default: launch_filter_t<4>(g, e, m); break;
+    case 1: launch_filter_t<1, R>(g, e, m); break;
+    case 2: launch_filter_t<2, R>(g, e, m); break;
+    case 8: launch_filter_t<8, R>(g, e, m); break;
+    default: launch_filter_t<4, R>(g, e, m); break;
   }
   const int B = g->tune.block;
   const unsigned blocks = blocks_for(m, B, g->tune.grid_cap);
   hipLaunchKernelGGL((k_link_live<Ord>), dim3(blocks), dim3(B), 0, g->stream, g->parent, g->live,
                      g->live_ctl, (int32_t)g->n, g->slots, g->flags);
-  hipLaunchKernelGGL(k_compress_live, dim3(blocks), dim3(B), 0, g->stream, g->parent, g->live, g->live_ctl,
+  hipLaunchKernelGGL(k_compress_live<R>, dim3(blocks), dim3(B), 0, g->stream, g->parent, g->live, g->live_ctl,
                      (int32_t)g->n, g->flags);
 }
 
@@ -471,6 +488,69 @@ int launch_bulk_find(cc_graph* g, const int2* items, int64_t count, uint8_t* out
   return launch_bulk_find_t<KIND, ById>(g, items, count, out);
 }
 
+// Compaction threshold: fold finished link-counter snapshots into the
+// live-fraction estimate and decide this update's schedule.
+bool choose_split(cc_graph* g) {
+  if (g->tune.split_below <= 0) return false;
+  if (g->capturing) return g->split_now;
+  for (int k = 0; k < 2; ++k) {
+    cc_graph::Snap& sn = g->snap[(g->snap_next + k) % 2];  // older first
+    if (!sn.pending || hipEventQuery(sn.done) != hipSuccess) continue;
+    sn.pending = false;
+    if (sn.epoch != g->epoch) continue;
+    int64_t links = 0;
+    for (int i = 0; i < kSlots; ++i) links += (int64_t)sn.host[(size_t)i * kSlotStride];
+    if (g->base_valid && sn.edges > g->base_edges)
+      g->live_est = (double)(links - g->base_links) / (double)(sn.edges - g->base_edges);
+    g->base_links = links;
+    g->base_edges = sn.edges;
+    g->base_valid = true;
+  }
+  g->split_now = g->epoch_edges > 0 && g->live_est * 100.0 < (double)g->tune.split_below;
+  return g->split_now;
+}
+
+// After an update under the threshold: copy the link counters to a free
+// pinned slot (never waits; skipped when both slots are still in flight).
+int snapshot_links(cc_graph* g, int64_t m) {
+  g->epoch_edges += m;
+  if (g->tune.split_below <= 0 || g->capturing) return CC_OK;
+  cc_graph::Snap& sn = g->snap[g->snap_next];
+  if (sn.pending) {
+    if (hipEventQuery(sn.done) != hipSuccess) return CC_OK;
+    (void)choose_split(g);  // fold it in before the slot is reused
+  }
+  if (!sn.host) {
+    if (hipHostMalloc((void**)&sn.host, (size_t)kSlots * kSlotStride * 8, hipHostMallocDefault) != hipSuccess) {
+      sn.host = nullptr;
+      cc_set_error("pinned allocation of a link-counter snapshot failed");
+      return CC_ENOMEM;
+    }
+    HIP_TRY(hipEventCreateWithFlags(&sn.done, hipEventDisableTiming));
+  }
+  HIP_TRY(hipMemcpyAsync(sn.host, g->slots, (size_t)kSlots * kSlotStride * 8, hipMemcpyDeviceToHost, g->stream));
+  HIP_TRY(hipEventRecord(sn.done, g->stream));
+  sn.pending = true;
+  sn.epoch = g->epoch;
+  sn.edges = g->epoch_edges;
+  g->snap_next = (g->snap_next + 1) % 2;
+  return CC_OK;
+}
+
+// A reset or load starts a new epoch of link counts (base: links 0, or the
+// image's, at edge 0).  Updates whose edges the host does not count (the
+// one-launch stream, Bulk-Find) also start one, with no base: the next
+// snapshot read becomes the base.
+void new_epoch(cc_graph* g, bool base_known = true) {
+  g->epoch++;
+  g->epoch_edges = 0;
+  g->base_links = 0;
+  g->base_edges = 0;
+  g->base_valid = base_known;
+  g->live_est = 1.0;
+  g->split_now = false;
+}
+
 // Host state after an update call, and the periodic full compression.
 void after_update(cc_graph* g) {
   g->updates++;
@@ -590,6 +670,10 @@ extern "C" int cc_destroy(cc_graph* g) {
   (void)hipFree(g->member);
   (void)hipFree(g->member_ctl);
   if (g->bf_ready) free_bulkfind(g);
+  for (auto& sn : g->snap) {
+    if (sn.done) (void)hipEventDestroy(sn.done);
+    if (sn.host) (void)hipHostFree(sn.host);
+  }
   delete g;
   return CC_OK;
 }
@@ -658,6 +742,7 @@ extern "C" int cc_reset(cc_graph* g) {
     g->cap_reset = true;
     g->cap_updates = 0;
   }
+  new_epoch(g);
   return launch_init(g);
 }
 
@@ -675,12 +760,13 @@ extern "C" int cc_bulk_update(cc_graph* g, const int32_t* edges, int64_t m) {
     if (rc == CC_OK) {
       g->updates++;
       g->pristine = false;
+      g->epoch_edges += m;
     }
     return rc;
   }
   const bool hashed = g->tune.hook == 1, ranked = g->tune.hook == 2;
-  if (ranked && g->tune.mode != 0) {
-    cc_set_error("cc_bulk_update: union by rank runs with the fused schedule only");
+  if (ranked && g->tune.mode == 2) {
+    cc_set_error("cc_bulk_update: union by rank does not run with the contracting schedule");
     return CC_EINVAL;
   }
   if (g->tune.mode == 2) {
@@ -695,7 +781,8 @@ extern "C" int cc_bulk_update(cc_graph* g, const int32_t* edges, int64_t m) {
     member_touched_invalid(g);
     int rc = hashed ? launch_contract_t<ByHash>(g, e, m) : launch_contract_t<ById>(g, e, m);
     if (rc != CC_OK) return rc;
-  } else if (g->tune.mode == 1) {
+  } else if (g->tune.mode == 1 ||
+             (choose_split(g) && m <= 0x7fffffffLL && !(g->capturing && m > g->live_cap))) {
     if (m > 0x7fffffffLL) {  // the live count is a 32-bit device counter
       cc_set_error("cc_bulk_update: the split update takes at most 2^31-1 edges per call");
       return CC_EINVAL;
@@ -708,7 +795,8 @@ extern "C" int cc_bulk_update(cc_graph* g, const int32_t* edges, int64_t m) {
     int rc = alloc_live(g, m);
     if (rc != CC_OK) return rc;
     member_touched_invalid(g);
-    if (hashed) launch_split_o<ByHash>(g, e, m);
+    if (ranked) launch_split_o<ByRank>(g, e, m);
+    else if (hashed) launch_split_o<ByHash>(g, e, m);
     else launch_split_o<ById>(g, e, m);
   } else {
     if (g->tune.compress_linked && !g->hooked) {
@@ -733,7 +821,7 @@ extern "C" int cc_bulk_update(cc_graph* g, const int32_t* edges, int64_t m) {
   }
   after_update(g);
   HIP_TRY(hipGetLastError());
-  return CC_OK;
+  return snapshot_links(g, m);
 }
 
 extern "C" int cc_bulk_update_noalloc(cc_graph* g, const int32_t* edges, int64_t m) {
@@ -756,6 +844,7 @@ extern "C" int cc_bulk_update_noalloc(cc_graph* g, const int32_t* edges, int64_t
   else if (g->tune.hook == 1) launch_fused_noalloc<ByHash>(g, e, m, sc);
   else launch_fused_noalloc<ById>(g, e, m, sc);
   after_update(g);
+  g->epoch_edges += m;
   HIP_TRY(hipGetLastError());
   return CC_OK;
 }
@@ -956,6 +1045,8 @@ extern "C" int cc_load(cc_graph* g, const void* host_buf) {
   HIP_TRY(hipMemcpyAsync(g->slots, h.data(), h.size() * 8, hipMemcpyHostToDevice, g->stream));
   if (g->member) member_reset(g, 0);  // its bits were proofs about the old forest
   g->pristine = false;
+  new_epoch(g);
+  g->base_links = hdr[1];
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(g->stream));
   return CC_OK;
@@ -1032,6 +1123,7 @@ extern "C" int cc_exec_launch(cc_exec* x) {
     g->pristine = false;
     g->updates += x->updates;
   }
+  if (x->resets || x->updates > 0) new_epoch(g, false);  // the replay's edge counts are not the host's
   // Filter bitmaps allocated after the capture were not kept by the
   // recorded kernels: after a recorded reset their bits are no proofs about
   // the new forest, and recorded updates may have linked vertices the
@@ -1102,6 +1194,7 @@ extern "C" int cc_bulk_stream(cc_graph* g, int64_t batches, const int32_t* edges
   if (batches == 0) return CC_OK;
   DeviceGuard dg(g->device);
   g->pristine = false;
+  new_epoch(g, false);  // its edge counts stay on the device
   member_touched_invalid(g);
   if (g->tune.hook == 1) return launch_stream<ByHash>(g, batches, edges, eoff, pairs, qoff, out, max_items);
   if (g->tune.hook == 2) return launch_stream<ByRank>(g, batches, edges, eoff, pairs, qoff, out, max_items);

@@ -313,7 +313,7 @@ extern "C" int cc_pool_set_stream(cc_pool* p, void* stream) {
 extern "C" int cc_pool_set_option(cc_pool* p, int key, int64_t value) {
   if (!p) return CC_EINVAL;
   if (key == CC_OPT_UPDATE_MODE || key == CC_OPT_COMPRESS_EVERY || key == CC_OPT_FIND || key == CC_OPT_FILTER ||
-      key == CC_OPT_QUERY_ITEMS) {
+      key == CC_OPT_QUERY_ITEMS || key == CC_OPT_SPLIT_BELOW) {
     cc_set_error("cc_pool_set_option: option %d does not apply to pools", key);
     return CC_EINVAL;
   }

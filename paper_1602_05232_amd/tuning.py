@@ -14,7 +14,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuned.json")
 DEFAULTS = {"update_mode": 0, "block": 256, "items": 0, "query_halving": 1, "compress_every": 0,
-            "hook": 0, "grid_cap": 4096, "compress_linked": 1, "filter": 0, "query_items": 0}
+            "hook": 0, "grid_cap": 4096, "compress_linked": 1, "filter": 0, "query_items": 0, "split_below": 0}
 
 
 def _load():

@@ -159,7 +159,7 @@ def test_serve64_trace_full(cc, trace):
     from paper_1602_05232_amd import serve, tuning
     t, dev, want = trace
     n = 1 << SCALE
-    popts = tuning.lookup("pool", "mixed", n) or {}
+    popts = tuning.lookup("serve", "rmat", n) or tuning.lookup("pool", "mixed", n) or {}
     popts = {k: v for k, v in popts.items() if k not in ("update_mode", "compress_every")}
     popts["compress_linked"] = 0
     print("serving, options %s" % popts, flush=True)

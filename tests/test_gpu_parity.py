@@ -38,6 +38,11 @@ OPTION_SETS = [
     dict(update_mode=1, filter=2),
     dict(update_mode=0, hook=2, filter=2, items=1, query_items=4, block=512, grid_cap=768, compress_linked=0),
     dict(update_mode=0, query_items=8, block=128),
+    dict(update_mode=1, hook=2),
+    dict(update_mode=1, hook=2, items=8, block=256, query_halving=0),
+    dict(update_mode=0, split_below=100, hook=2),
+    dict(update_mode=0, split_below=60, hook=0, compress_linked=0),
+    dict(update_mode=0, split_below=100, hook=1, filter=2),
 ]
 
 
@@ -211,13 +216,14 @@ def test_argument_errors(cc):
     g = cc.Graph(16)
     L = cc.lib()
     assert L.cc_set_option(g.handle, 6, 3) == cc.cc.CC_EINVAL
-    for mode in (1, 2):
-        g2 = cc.Graph(16, hook=2, update_mode=mode)  # rank linking needs the fused schedule
-        assert L.cc_bulk_update(g2.handle, g2.handle, 0) == cc.cc.CC_OK
-        with pytest.raises(cc.CCError):
-            g2.bulk_update(dev([[1, 2]]))
-        assert g2.num_components() == 16
-        g2.close()
+    g2 = cc.Graph(16, hook=2, update_mode=2)  # rank linking does not run with the contracting schedule
+    assert L.cc_bulk_update(g2.handle, g2.handle, 0) == cc.cc.CC_OK
+    with pytest.raises(cc.CCError):
+        g2.bulk_update(dev([[1, 2]]))
+    assert g2.num_components() == 16
+    g2.close()
+    assert L.cc_set_option(g.handle, 14, 101) == cc.cc.CC_EINVAL  # compaction threshold is a percentage
+    assert L.cc_set_option(g.handle, 14, -1) == cc.cc.CC_EINVAL
     assert L.cc_set_option(g.handle, 1, 3) == cc.cc.CC_EINVAL
     assert L.cc_bulk_update(g.handle, None, 3) == cc.cc.CC_EINVAL
     assert L.cc_bulk_update(g.handle, None, -1) == cc.cc.CC_EINVAL
@@ -269,9 +275,9 @@ def test_linking_order_is_fixed_until_reset(cc):
     the order may change only on a fresh forest; a rejected update leaves the
     graph fresh."""
     s = synth.rmat_stream(scale=12, size_lo=6, size_hi=11, qbatch=256)
-    g = cc.Graph(s.n, hook=2, update_mode=1)
+    g = cc.Graph(s.n, hook=2, update_mode=2)
     with pytest.raises(cc.CCError):
-        g.bulk_update(dev(s.batch(0)))  # rank needs the fused schedule: nothing runs
+        g.bulk_update(dev(s.batch(0)))  # rank does not run with the contracting schedule: nothing runs
     g.set_option("hook", 1)  # still fresh
     g.set_option("update_mode", 0)
     ref = oracle.UnionFind(s.n)
