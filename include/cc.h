@@ -101,9 +101,14 @@ enum cc_option {
    * (with path halving; default).  1 = Bulk-Find (Section 5, Algorithm 4):
    * all endpoints of a Bulk-Update or Bulk-Query are resolved together, flows
    * that meet are merged, and every traversed vertex is pointed at its root;
-   * one cooperative launch per bulk operation; scratch of about 8 bytes per
-   * vertex plus 8 bytes per item of the largest bulk operation; not
-   * available during capture. */
+   * Phase II by pointer jumping over the traversed vertices.  2 = Bulk-Find
+   * with Phase II as the paper's top-down distribution through the response
+   * distributor (Section 5.1: the traversed parent pointers sorted by a hash
+   * of the parent into 3x as many buckets, then handed the root level by
+   * level from the roots; about 52 more bytes per traversal bound entry,
+   * 2 * (vertices + items), at most 2^31 - 1 of them).  One cooperative launch
+   * per bulk operation; scratch of about 8 bytes per vertex plus 8 bytes per
+   * item of the largest bulk operation; not available during capture. */
   CC_OPT_FIND = 10,
   /* Pools only (cc_pool_run): 1 = all rounds of a run in one cooperative
    * launch, separated by device-wide barriers, instead of one launch per

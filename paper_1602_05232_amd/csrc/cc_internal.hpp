@@ -101,7 +101,7 @@ inline bool set_tuning(Tuning* t, int key, int64_t v) {
       t->spin_limit = v;
       return true;
     case CC_OPT_FIND:
-      if (v != 0 && v != 1) return false;
+      if (v < 0 || v > 2) return false;
       t->find = (int)v;
       return true;
     case CC_OPT_ONE_LAUNCH:

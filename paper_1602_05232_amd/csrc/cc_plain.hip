@@ -177,8 +177,48 @@ int alloc_hooked(cc_graph* g) {
   return CC_OK;
 }
 
+void free_rd(cc_graph* g) {
+  BulkFindScratch& b = g->bf;
+  (void)hipFree(b.rd_cnt);
+  (void)hipFree(b.rd_off);
+  (void)hipFree(b.rd_pairs);
+  (void)hipFree(b.rd_down);
+  (void)hipFree(b.rd_big);
+  b.rd_cnt = b.rd_off = nullptr;
+  b.rd_pairs = b.rd_down = nullptr;
+  b.rd_big = nullptr;
+  b.rd_cap = 0;
+}
+
+// The response distributor's arrays for trails of up to cap entries (about
+// 52 bytes per entry).
+int alloc_rd(cc_graph* g, int64_t cap) {
+  BulkFindScratch& b = g->bf;
+  if (b.rd_cap >= cap) return CC_OK;
+  if (cap > 0x7fffffffLL) {
+    cc_set_error("Bulk-Find with the response distributor: a trail bound of %lld entries exceeds 2^31 - 1",
+                 (long long)cap);
+    return CC_EINVAL;
+  }
+  HIP_TRY(hipStreamSynchronize(g->stream));
+  free_rd(g);
+  const size_t words = 3 * (size_t)cap + 1;
+  bool ok = hipMalloc(&b.rd_cnt, words * 4) == hipSuccess && hipMalloc(&b.rd_off, words * 4) == hipSuccess &&
+            hipMalloc(&b.rd_pairs, (size_t)cap * sizeof(int2)) == hipSuccess &&
+            hipMalloc(&b.rd_down, 2 * (size_t)cap * sizeof(int2)) == hipSuccess &&
+            hipMalloc(&b.rd_big, (size_t)cap * 4) == hipSuccess;
+  if (!ok) {
+    free_rd(g);
+    cc_set_error("Bulk-Find: response distributor allocation (%lld entries) failed", (long long)cap);
+    return CC_ENOMEM;
+  }
+  b.rd_cap = cap;
+  return CC_OK;
+}
+
 void free_bulkfind(cc_graph* g) {
   BulkFindScratch& b = g->bf;
+  free_rd(g);
   (void)hipFree(b.visited);
   (void)hipFree(b.seg0);
   (void)hipFree(b.log);
@@ -386,11 +426,11 @@ int read_links(cc_graph* g, unsigned long long* links) {
   return CC_OK;
 }
 
-template <int KIND, class Ord>
+template <int KIND, class Ord, int PH2>
 int launch_bulk_find_t(cc_graph* g, const int2* items, int64_t count, uint8_t* out) {
   const int block = 256;
   int per_cu = 0, cus = 0;
-  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bulk_find<KIND, Ord>, block, 0));
+  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bulk_find<KIND, Ord, PH2>, block, 0));
   HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device));
   int64_t grid = (2 * count + block - 1) / block;
   grid = std::min<int64_t>(std::min<int64_t>(grid, cc::coop_limit(per_cu, cus)), 1024);
@@ -410,6 +450,10 @@ int launch_bulk_find_t(cc_graph* g, const int2* items, int64_t count, uint8_t* o
     g->bf_seg0_entries = seg0_cap * grid;
   }
   g->bf.seg0_cap = seg0_cap;
+  if (PH2 == 1) {
+    const int rc = alloc_rd(g, seg0_cap * grid + g->bf.log_cap);
+    if (rc != CC_OK) return rc;
+  }
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, g->stream, g->bf.ctl, kBulkFindCtlWords);
   HIP_TRY(hipGetLastError());
   int32_t* parent = g->parent;
@@ -420,8 +464,8 @@ int launch_bulk_find_t(cc_graph* g, const int2* items, int64_t count, uint8_t* o
   unsigned spin = (unsigned)g->tune.spin_limit;
   void* args[] = {&parent, &items, &count, &n, &out, &sc, &slots, &flags, &spin};
   if (const int crc = cc::coop_before(g->stream)) return crc;
-  HIP_TRY(hipLaunchCooperativeKernel((const void*)k_bulk_find<KIND, Ord>, dim3((unsigned)grid), dim3(block), args,
-                                     0, g->stream));
+  HIP_TRY(hipLaunchCooperativeKernel((const void*)k_bulk_find<KIND, Ord, PH2>, dim3((unsigned)grid), dim3(block),
+                                     args, 0, g->stream));
   if (const int crc = cc::coop_after(g->stream)) return crc;
   return CC_OK;
 }
@@ -483,9 +527,14 @@ int launch_bulk_find(cc_graph* g, const int2* items, int64_t count, uint8_t* out
   }
   int rc = alloc_bulkfind(g);
   if (rc != CC_OK) return rc;
-  if (g->tune.hook == 1) return launch_bulk_find_t<KIND, ByHash>(g, items, count, out);
-  if (g->tune.hook == 2) return launch_bulk_find_t<KIND, ByRank>(g, items, count, out);
-  return launch_bulk_find_t<KIND, ById>(g, items, count, out);
+  if (g->tune.find == 2) {
+    if (g->tune.hook == 1) return launch_bulk_find_t<KIND, ByHash, 1>(g, items, count, out);
+    if (g->tune.hook == 2) return launch_bulk_find_t<KIND, ByRank, 1>(g, items, count, out);
+    return launch_bulk_find_t<KIND, ById, 1>(g, items, count, out);
+  }
+  if (g->tune.hook == 1) return launch_bulk_find_t<KIND, ByHash, 0>(g, items, count, out);
+  if (g->tune.hook == 2) return launch_bulk_find_t<KIND, ByRank, 0>(g, items, count, out);
+  return launch_bulk_find_t<KIND, ById, 0>(g, items, count, out);
 }
 
 // Compaction threshold: fold finished link-counter snapshots into the
@@ -754,7 +803,7 @@ extern "C" int cc_bulk_update(cc_graph* g, const int32_t* edges, int64_t m) {
   if (m == 0) return CC_OK;
   DeviceGuard dg(g->device);
   const int2* e = reinterpret_cast<const int2*>(edges);
-  if (g->tune.find == 1) {
+  if (g->tune.find != 0) {
     member_touched_invalid(g);
     int rc = launch_bulk_find<0>(g, e, m, nullptr);
     if (rc == CC_OK) {
@@ -857,7 +906,7 @@ extern "C" int cc_bulk_query(cc_graph* g, const int32_t* pairs, int64_t q, uint8
   if (q == 0) return CC_OK;
   DeviceGuard dg(g->device);
   const int2* p = reinterpret_cast<const int2*>(pairs);
-  if (g->tune.find == 1) return launch_bulk_find<1>(g, p, q, out);
+  if (g->tune.find != 0) return launch_bulk_find<1>(g, p, q, out);
   const bool ranked = g->tune.hook == 2;
   if (g->tune.query_halving) {
     if (ranked) launch_query_h<true, true>(g, p, q, out);

@@ -16,11 +16,16 @@
 //    an ancestor-or-self of the true root, equal roots still prove
 //    connectivity (connectivity only grows), and a link attempt on a stale
 //    root fails its CAS, which returns the fresh parent to continue from.
-//  * Path halving re-points each visited node at its grandparent with a plain
-//    store.  A store only ever targets a non-root (a node seen with a parent
-//    other than itself never becomes a root again) and writes one of its
-//    ancestors, so it can never undo a link or create a cycle, whatever order
-//    the stores land in.
+//  * Path halving re-points each visited node at its grandparent with a
+//    relaxed store.  A store only ever targets a non-root (a node seen with a
+//    parent other than itself never becomes a root again) and writes one of
+//    its ancestors, so it can never undo a link or create a cycle, whatever
+//    order the stores land in.  The store is made at agent scope: at
+//    workgroup scope such a store was measured to stay invisible to loads
+//    from other XCDs well into the next kernel (Bulk-Find's first parent
+//    reads returned the value from before the previous kernel's compression,
+//    a few times per million trail vertices), which finds tolerate but any
+//    operation that must read one parent value consistently does not.
 //  * Every walk counts its steps (unsigned, so the count cannot overflow
 //    before it passes n, even at n = 2^31 - 1); more than n steps means the
 //    array holds a cycle, which is latched as "corrupt" and ends the walk.
@@ -45,7 +50,7 @@ __device__ __forceinline__ int ld(const int32_t* p) {
   return __hip_atomic_load(const_cast<int32_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 __device__ __forceinline__ void st(int32_t* p, int32_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 // Device-scope CAS; returns the value found (== expected on success).
 __device__ __forceinline__ int32_t cas(int32_t* p, int32_t expected, int32_t desired) {

@@ -78,7 +78,8 @@ def test_tuned_options_are_known_and_in_range():
     from paper_1602_05232_amd import cc, tuning
     allowed = {"update_mode": {0, 1, 2}, "block": set(range(64, 1025, 64)), "items": {0, 1, 2, 4, 8},
                "query_items": {0, 1, 2, 4, 8}, "query_halving": {0, 1}, "hook": {0, 1, 2},
-               "compress_linked": {0, 1}, "filter": {0, 1, 2}, "find": {0, 1}, "one_launch": {0, 1}}
+               "compress_linked": {0, 1}, "filter": {0, 1, 2}, "find": {0, 1, 2}, "one_launch": {0, 1},
+               "split_below": set(range(0, 101))}
     tab = json.load(open(tuning.CACHE))
     assert "plain/rmat/24" in tab
     for key, opts in list(tab.items()) + [("defaults", tuning.DEFAULTS)]:

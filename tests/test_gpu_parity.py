@@ -31,6 +31,9 @@ OPTION_SETS = [
     dict(find=1, hook=1, grid_cap=16),
     dict(find=1),
     dict(find=1, hook=2),
+    dict(find=2),
+    dict(find=2, hook=1, grid_cap=3),
+    dict(find=2, hook=2, grid_cap=16),
     dict(update_mode=0, filter=2),
     dict(update_mode=0, hook=1, filter=1, items=8, grid_cap=5),
     dict(update_mode=0, hook=2, filter=1, compress_linked=0),
@@ -170,7 +173,7 @@ def test_edge_cases(cc, mode):
 
 @pytest.mark.parametrize("opts", [dict(update_mode=0), dict(update_mode=1), dict(update_mode=0, hook=1),
                                   dict(update_mode=0, hook=2), dict(update_mode=2), dict(update_mode=2, hook=1),
-                                  dict(find=1), dict(find=1, hook=2)],
+                                  dict(find=1), dict(find=1, hook=2), dict(find=2), dict(find=2, hook=2)],
                          ids=opt_id)
 def test_deep_chain(cc, opts):
     # reversed path in one minibatch, then in single-edge minibatches
@@ -353,7 +356,8 @@ def test_order_independence_and_reset(cc):
     g.close()
 
 
-def test_bulk_find_worked_example(cc):
+@pytest.mark.parametrize("find", [1, 2], ids=["jumping", "response-distributor"])
+def test_bulk_find_worked_example(cc, find):
     """Section 5's example: a tree rooted at 19 in which the finds of 1 and 7
     meet at 4 (1 -> 2 -> 4 and 7 -> 8 -> 9 -> 4) and the find of 3 joins 1's
     flow at 2.  After Bulk-Find of {1, 3, 4, 7} every traversed vertex points
@@ -365,7 +369,7 @@ def test_bulk_find_worked_example(cc):
     for c, p in ((1, 2), (3, 2), (2, 4), (7, 8), (8, 9), (9, 4), (4, 19)):
         par[c] = p
     img = bytearray(np.array([n, 7], np.int64).tobytes() + par.tobytes())
-    g = cc.Graph(n, hook=2, find=1)
+    g = cc.Graph(n, hook=2, find=find)
     g.load(img)
     ans = g.bulk_query(dev([[1, 3], [4, 7], [1, 19], [5, 19]])).cpu().numpy()
     np.testing.assert_array_equal(ans, [1, 1, 1, 0])
@@ -377,7 +381,8 @@ def test_bulk_find_worked_example(cc):
     g.close()
 
 
-@pytest.mark.parametrize("opts", [dict(find=1), dict(find=1, grid_cap=5), dict(find=1, hook=2, grid_cap=64)],
+@pytest.mark.parametrize("opts", [dict(find=1), dict(find=1, grid_cap=5), dict(find=1, hook=2, grid_cap=64),
+                                  dict(find=2), dict(find=2, grid_cap=5), dict(find=2, hook=2, grid_cap=64)],
                          ids=opt_id)
 def test_bulk_find_wide_levels(cc, opts):
     """Minibatches large enough that Bulk-Find's levels are appended in
@@ -395,9 +400,10 @@ def test_bulk_find_wide_levels(cc, opts):
     run_parity(cc, s, opts)
 
 
-def test_bulk_find_compresses_every_endpoint(cc):
+@pytest.mark.parametrize("find", [1, 2], ids=["jumping", "response-distributor"])
+def test_bulk_find_compresses_every_endpoint(cc, find):
     s = synth.rmat_stream(scale=15, size_lo=10, size_hi=14, qbatch=1 << 12)
-    g = cc.Graph(s.n, find=1, hook=2)
+    g = cc.Graph(s.n, find=find, hook=2)
     ref = oracle.UnionFind(s.n)
     for i in range(s.num_batches):
         g.bulk_update(dev(s.batch(i)))

@@ -10,7 +10,7 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
-SCHEDULES = [dict(update_mode=0), dict(update_mode=1), dict(update_mode=2), dict(find=1)]
+SCHEDULES = [dict(update_mode=0), dict(update_mode=1), dict(update_mode=2), dict(find=1), dict(find=2)]
 
 
 def case_options(rng):
