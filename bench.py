@@ -574,7 +574,7 @@ def run_batched(args):
     # each candidate set (one step each), then the fastest is timed.
     candidates = [dict(), dict(hook=2, compress_linked=0), dict(hook=1, compress_linked=0),
                   dict(hook=2, compress_linked=0, block=1024), dict(hook=2, compress_linked=0, filter=2)]
-    graphs = [ccgpu.Graph(s.n) for s in streams]
+    graphs = [] if args.no_plain else [ccgpu.Graph(s.n) for s in streams]
     out_plain = torch.empty_like(out)
 
     def set_plain_options(o):
@@ -608,6 +608,8 @@ def run_batched(args):
         torch.cuda.synchronize()
         return time.perf_counter() - t0
 
+    if args.no_plain:  # the pool forms only (for profiling runs)
+        candidates = []
     trial = []
     for o in candidates:
         set_plain_options(o)
@@ -616,11 +618,15 @@ def run_batched(args):
         plain_step()
         trial.append((time.perf_counter() - t0, o))
         log("per-graph trial %s: %.1f ms" % (o, trial[-1][0] * 1e3))
-    plain_opts = min(trial, key=lambda x: x[0])[1]
-    set_plain_options(plain_opts)
-    wall_plain = timed(plain_step, "per-graph")
     wall_pool = timed(pool_step, "pool")
-    assert torch.equal(out, out_plain), "pool answers differ from per-graph answers"
+    if args.no_plain:
+        plain_opts, wall_plain = None, float("nan")
+        out_plain.copy_(out)
+    else:
+        plain_opts = min(trial, key=lambda x: x[0])[1]
+        set_plain_options(plain_opts)
+        wall_plain = timed(plain_step, "per-graph")
+        assert torch.equal(out, out_plain), "pool answers differ from per-graph answers"
     # the same run with all rounds of a step in one cooperative launch
     ops_all = pool.prepare([op for ops in ops_per_step for op in ops])
     pool.set_option("one_launch", 1)
@@ -635,7 +641,7 @@ def run_batched(args):
     assert torch.equal(out, out_plain), "one-launch pool answers differ from per-graph answers"
     pool.set_option("one_launch", 0)
     comps = sum(pool.num_components(i) for i in ids)
-    assert comps == sum(gr.num_components() for gr in graphs)
+    assert args.no_plain or comps == sum(gr.num_components() for gr in graphs)
     for gr in graphs:
         gr.close()
     pool.close()
@@ -931,6 +937,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="batched1024 only: skip the per-graph form (profiling runs of the pool)")
     ap.add_argument("--no-forms", action="store_true",
                     help="rmat24 only: skip the other workloads' forms (plain vs batched vs served)")
     args = ap.parse_args()
