@@ -146,12 +146,15 @@ inline bool get_tuning(const Tuning* t, int key, int64_t* v) {
 }
 
 // Upper bound on the blocks of a cooperative launch (every block resident
-// at once).  One block per compute unit is left free: a kernel whose
-// registers fill the register file at the occupancy calculator's maximum did
-// not get every block of such a grid resident at the same time (the device
-// barrier then waited out its spin limit), while one block less per CU did.
+// at once): the occupancy calculator's blocks per compute unit times the
+// units.  Measured on an idle device, grids of that size became resident at
+// once for every register footprint tried (the calculator is conservative
+// above 62 VGPRs); what can keep a grid from becoming resident is another
+// cooperative grid holding compute units, which coop_before/coop_after rule
+// out for this library's launches.  A grid that still cannot become
+// resident ends at the barrier's spin limit with CC_EDEVICE.
 inline int64_t coop_limit(int per_cu, int cus) {
-  return (int64_t)(per_cu > 1 ? per_cu - 1 : 1) * cus;
+  return (int64_t)(per_cu > 0 ? per_cu : 1) * cus;
 }
 
 // Cooperative launches of this library never overlap on a device.  Each

@@ -25,7 +25,11 @@
 //    from other XCDs well into the next kernel (Bulk-Find's first parent
 //    reads returned the value from before the previous kernel's compression,
 //    a few times per million trail vertices), which finds tolerate but any
-//    operation that must read one parent value consistently does not.
+//    operation that must read one parent value consistently does not.  A
+//    translation unit whose forests Bulk-Find never reads (the pool's) may
+//    define CC_PATH_STORE_SCOPE as workgroup scope before including this
+//    header; everything here sits in an unnamed namespace, so each unit
+//    keeps its own definitions.
 //  * Every walk counts its steps (unsigned, so the count cannot overflow
 //    before it passes n, even at n = 2^31 - 1); more than n steps means the
 //    array holds a cycle, which is latched as "corrupt" and ends the walk.
@@ -38,7 +42,12 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#ifndef CC_PATH_STORE_SCOPE
+#define CC_PATH_STORE_SCOPE __HIP_MEMORY_SCOPE_AGENT
+#endif
+
 namespace ccdev {
+namespace {
 
 constexpr int kFlagRange = 1;
 constexpr int kFlagCorrupt = 2;
@@ -49,8 +58,10 @@ constexpr int kSlotStride = 16;  // 16 x u64 = 128 B between counters
 __device__ __forceinline__ int ld(const int32_t* p) {
   return __hip_atomic_load(const_cast<int32_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
+// A path-shortening store (halving, compression): relaxed, at the scope
+// described above.
 __device__ __forceinline__ void st(int32_t* p, int32_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, CC_PATH_STORE_SCOPE);
 }
 // Device-scope CAS; returns the value found (== expected on success).
 __device__ __forceinline__ int32_t cas(int32_t* p, int32_t expected, int32_t desired) {
@@ -284,4 +295,5 @@ __device__ __forceinline__ void count_links(unsigned long long* slots, int links
   }
 }
 
+}  // namespace
 }  // namespace ccdev
