@@ -147,6 +147,10 @@ def tune_stream(stream, reps=3, log=print):
 def pool_candidates(quick=False):
     out = [dict(block=b, items=i, hook=h, compress_linked=c)
            for b, i, h, c in itertools.product((256, 512, 1024), (0, 4, 8), (0, 1, 2), (0, 1))]
+    # launch width (blocks that stride over the tiles) for the family that
+    # wins above: union by rank without linked-root compression
+    out += [dict(block=b, items=i, hook=2, compress_linked=0, grid_cap=g)
+            for b, i, g in itertools.product((256, 512, 1024), (0, 4), (1024, 2048, 8192))]
     return out[::5] if quick else out
 
 
