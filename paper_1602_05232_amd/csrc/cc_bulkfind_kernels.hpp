@@ -106,6 +106,14 @@ struct LevelOut {
   long long cap;
 };
 
+// Root entries of the top-down list are appended in chunks of kRdRootChunk
+// per block (one atomic per chunk: exact appends, one atomic per wavefront
+// on the one counter, took 0.4 ms of a 1.4 ms query call on the R-MAT
+// stream).  A block's last chunk is padded, so the list holds up to
+// kRdRootPad more entries: blocks of 256 threads, at most 1024 of them.
+constexpr int kRdRootChunk = 512;
+constexpr int64_t kRdRootPad = 1024 * (int64_t)kRdRootChunk;
+
 // Bucket sizes served by one thread, and above which the whole grid serves
 // a bucket (between the two: one block).
 constexpr int kRdThread = 16;
@@ -122,7 +130,7 @@ struct BulkFindScratch {
   uint32_t* rd_cnt;   // 3 * rd_cap + 1: bucket counts, then scatter cursors
   uint32_t* rd_off;   // 3 * rd_cap + 1: bucket offsets
   int2* rd_pairs;     // rd_cap: (parent(x), x), sorted by bucket
-  int2* rd_down;      // 2 * rd_cap: (vertex, root) of the top-down levels, (-1, -1) in chunk padding
+  int2* rd_down;      // 2 * rd_cap + kRdRootPad: (vertex, root) of the top-down levels, (-1, -1) in chunk padding
   int32_t* rd_big;    // rd_cap: top-down entries whose bucket a block serves (from the front) or the grid
                       // serves (from the back); together at most one level's entries
   int64_t rd_cap;
@@ -394,7 +402,7 @@ __global__ void k_bulk_find(int32_t* __restrict__ parent, const int2* __restrict
     uint32_t* cnt = sc.rd_cnt;
     uint32_t* off = sc.rd_off;
     unsigned* blk = sc.ctl + kBfRd + 384;
-    const long long dcap = 2 * sc.rd_cap;
+    const long long dcap = 2 * sc.rd_cap + kRdRootPad;
     if (tid == 0) {
       chunk[0] = -1;
       chunk[1] = 0;
@@ -439,14 +447,17 @@ __global__ void k_bulk_find(int32_t* __restrict__ parent, const int2* __restrict
     const int32_t hot = hot_key[16];
     alive = alive && grid_sync(bar, gen, flags, spin_limit);
     // (b) histogram of the pairs by bucket; the roots form level 0 of the
-    //     top-down list (exact appends: no padding before level 1)
+    //     top-down list (chunks of kRdRootChunk per block, the real count
+    //     in the level's ring word)
     const LevelOut roots{ring_ctr(sc.ctl, kBfRd, 0), 0, dcap};
+    int nroots = 0;
     for (int64_t base = 0; alive && base < cnt0; base += B) {
       const int64_t j = base + tid;
       const int32_t v = j < cnt0 ? seg[j] : -1;
       const int32_t p = v >= 0 ? ldp<R>(parent + v) : -1;
       hist_add(cnt, p, rho, v >= 0 && p != v, hot, hot_ctr);
-      level_put(v >= 0 && p == v, make_int2(v, v), sc.rd_down, roots, 0, chunk, wave_off, flags);
+      nroots += v >= 0 && p == v;
+      level_put(v >= 0 && p == v, make_int2(v, v), sc.rd_down, roots, kRdRootChunk, chunk, wave_off, flags);
     }
     for (int64_t base = 0; alive && base < lend; base += gsize) {
       const int64_t j = base + gtid;
@@ -454,9 +465,17 @@ __global__ void k_bulk_find(int32_t* __restrict__ parent, const int2* __restrict
       if ((uint32_t)v >= (uint32_t)n) v = -1;
       const int32_t p = v >= 0 ? ldp<R>(parent + v) : -1;
       hist_add(cnt, p, rho, v >= 0 && p != v, hot, hot_ctr);
-      level_put(v >= 0 && p == v, make_int2(v, v), sc.rd_down, roots, 0, chunk, wave_off, flags);
+      nroots += v >= 0 && p == v;
+      level_put(v >= 0 && p == v, make_int2(v, v), sc.rd_down, roots, kRdRootChunk, chunk, wave_off, flags);
     }
     __syncthreads();
+    if (chunk[0] >= 0)
+      for (long long t = chunk[1] + tid; t < kRdRootChunk; t += B) sc.rd_down[chunk[0] + t] = make_int2(-1, -1);
+    {
+      int block_roots;
+      (void)block_scan(nroots, &block_roots, wave_off);
+      if (tid == 0 && block_roots > 0) atomicAdd(ring_word(sc.ctl, kBfRd + 192, 0), (unsigned)block_roots);
+    }
     if (tid == 0 && hot >= 0 && hot_ctr[0] > 0u) atomicAdd(cnt + rd_bucket(hot, rho), hot_ctr[0]);
     alive = alive && grid_sync(bar, gen, flags, spin_limit);
     // (c) exclusive scan of the counts into the offsets: block b scans its
@@ -524,7 +543,7 @@ __global__ void k_bulk_find(int32_t* __restrict__ parent, const int2* __restrict
       const long long h = (long long)ld_ctr(roots.ctr);
       de = h < dcap ? h : dcap;
     }
-    long long real = de;  // entries of the current level without padding (level 0 was appended exactly)
+    long long real = alive ? (long long)ld_count(ring_word(sc.ctl, kBfRd + 192, 0)) : 0;  // level 0's entries without padding
     for (int level = 0; alive && de > ds; ++level) {
       unsigned* bighead = ring_word(sc.ctl, kBfRd + 96, level);
       unsigned* hubhead = ring_word(sc.ctl, kBfRd + 288, level);

@@ -191,7 +191,7 @@ void free_rd(cc_graph* g) {
 }
 
 // The response distributor's arrays for trails of up to cap entries (about
-// 52 bytes per entry).
+// 52 bytes per entry, plus 4 MiB of root-chunk padding).
 int alloc_rd(cc_graph* g, int64_t cap) {
   BulkFindScratch& b = g->bf;
   if (b.rd_cap >= cap) return CC_OK;
@@ -205,7 +205,7 @@ int alloc_rd(cc_graph* g, int64_t cap) {
   const size_t words = 3 * (size_t)cap + 1;
   bool ok = hipMalloc(&b.rd_cnt, words * 4) == hipSuccess && hipMalloc(&b.rd_off, words * 4) == hipSuccess &&
             hipMalloc(&b.rd_pairs, (size_t)cap * sizeof(int2)) == hipSuccess &&
-            hipMalloc(&b.rd_down, 2 * (size_t)cap * sizeof(int2)) == hipSuccess &&
+            hipMalloc(&b.rd_down, (2 * (size_t)cap + (size_t)kRdRootPad) * sizeof(int2)) == hipSuccess &&
             hipMalloc(&b.rd_big, (size_t)cap * 4) == hipSuccess;
   if (!ok) {
     free_rd(g);
