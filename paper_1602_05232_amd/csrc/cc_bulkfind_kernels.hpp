@@ -304,6 +304,7 @@ __global__ void k_bulk_find(int32_t* __restrict__ parent, const int2* __restrict
   __shared__ int32_t hot_key[17];   // response distributor: per-wavefront candidates, [16] the block's hot parent
   __shared__ int hot_votes[16];
   __shared__ unsigned hot_ctr[3];   // hot pairs counted, placed, and the base of the block's range
+  __shared__ int pass_max[16];      // top-down phase A: longest short bucket per wavefront
   const int B = blockDim.x, tid = threadIdx.x;
   const int64_t gsize = (int64_t)gridDim.x * B;
   const int64_t gtid = (int64_t)blockIdx.x * B + tid;
@@ -498,14 +499,25 @@ __global__ void k_bulk_find(int32_t* __restrict__ parent, const int2* __restrict
       int tot;
       (void)block_scan(pre, &tot, wave_off);
       unsigned run = (unsigned)tot;  // sum of the blocks before this one
-      for (int64_t t0 = c0; t0 < c1; t0 += B) {
-        const int64_t i = t0 + tid;
-        const int c = i < c1 ? (int)cnt[i] : 0;
+      // tiles of 8 consecutive buckets per thread: one block scan per 8 * B
+      for (int64_t t0 = c0; t0 < c1; t0 += (int64_t)B * 8) {
+        const int64_t i0 = t0 + (int64_t)tid * 8;
+        unsigned c[8];
+        unsigned sum = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          c[k] = i0 + k < c1 ? cnt[i0 + k] : 0u;
+          sum += c[k];
+        }
         int tile;
-        const int o = block_scan(c, &tile, wave_off);
-        if (i < c1) {
-          off[i] = run + (unsigned)o;
-          cnt[i] = run + (unsigned)o;  // scatter cursor
+        unsigned at = run + (unsigned)block_scan((int)sum, &tile, wave_off);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          if (i0 + k < c1) {
+            off[i0 + k] = at;
+            cnt[i0 + k] = at;  // scatter cursor
+          }
+          at += c[k];
         }
         run += (unsigned)tile;
       }
@@ -583,7 +595,18 @@ __global__ void k_bulk_find(int32_t* __restrict__ parent, const int2* __restrict
             hi = lo;
           }
         }
-        for (int it = 0; it < kRdThread; ++it) {  // uniform trip count: the appends are collective
+        // as many passes as the block's longest short bucket (most are empty
+        // or hold a pair or two); the trip count is block-uniform, since the
+        // appends are collective
+        int need = (int)(hi - lo);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) need = max(need, __shfl_xor(need, o, 64));
+        if ((tid & 63) == 0) pass_max[tid >> 6] = need;
+        __syncthreads();
+        int passes = 0;
+        for (int w = 0; w < (B >> 6); ++w) passes = max(passes, pass_max[w]);
+        __syncthreads();  // pass_max is rewritten in the next iteration
+        for (int it = 0; it < passes; ++it) {
           const bool have = lo + (uint32_t)it < hi;
           const int2 pr = have ? sc.rd_pairs[lo + it] : make_int2(-1, -1);
           const bool go = have && pr.x == d.x;
