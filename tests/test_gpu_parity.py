@@ -400,6 +400,38 @@ def test_bulk_find_wide_levels(cc, opts):
     run_parity(cc, s, opts)
 
 
+@pytest.mark.parametrize("opts", [dict(find=2), dict(find=2, grid_cap=1), dict(find=2, grid_cap=3),
+                                  dict(find=2, hook=2), dict(find=1, grid_cap=3)], ids=opt_id)
+def test_bulk_find_hubs(cc, opts):
+    """Stars of very different sizes (2^18 leaves down to a few) linked in
+    one minibatch, then queried from their leaves while a chain grows under
+    the leaves: the response distributor's hub buckets (served by the grid),
+    each block's hot parent (counted and placed through shared memory), the
+    other buckets of the same blocks, and root entries appended in chunks
+    all meet in one call.  Compared with the oracle answer by answer."""
+    n = 1 << 20
+    rng = np.random.default_rng(11)
+    centres = [0, 1, 2, 3, 4]
+    sizes = [1 << 18, 1 << 16, 1 << 12, 300, 7]
+    leaves = rng.permutation(np.arange(5, n, dtype=np.int32))
+    star, at = [], 0
+    for c, k in zip(centres, sizes):
+        star.append(np.stack([np.full(k, c, np.int32), leaves[at:at + k]], 1))
+        at += k
+    star = np.concatenate(star)[rng.permutation(sum(sizes))]
+    # chains hanging off leaves of every star, and a few random edges
+    tail = leaves[at:at + (1 << 16)]
+    heads = star[rng.integers(0, len(star), 1 << 16), 1]
+    chain = np.stack([heads, tail], 1).astype(np.int32)
+    rand = synth.uniform_pairs(synth.key(31, 0, 1), 0, 1 << 14, n)
+    edges = np.concatenate([star, chain, rand])
+    bsizes = [len(star), len(chain), len(rand)]
+    picks = np.concatenate([star[:, 1], tail])
+    q = picks[rng.integers(0, len(picks), (3 << 18, 2))].astype(np.int32)
+    s = synth.Stream("hubs", n, edges, synth._offsets(bsizes), q, synth._offsets([1 << 18] * 3))
+    run_parity(cc, s, opts)
+
+
 @pytest.mark.parametrize("find", [1, 2], ids=["jumping", "response-distributor"])
 def test_bulk_find_compresses_every_endpoint(cc, find):
     s = synth.rmat_stream(scale=15, size_lo=10, size_hi=14, qbatch=1 << 12)
