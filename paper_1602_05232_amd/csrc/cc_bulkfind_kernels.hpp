@@ -499,25 +499,14 @@ __global__ void k_bulk_find(int32_t* __restrict__ parent, const int2* __restrict
       int tot;
       (void)block_scan(pre, &tot, wave_off);
       unsigned run = (unsigned)tot;  // sum of the blocks before this one
-      // tiles of 8 consecutive buckets per thread: one block scan per 8 * B
-      for (int64_t t0 = c0; t0 < c1; t0 += (int64_t)B * 8) {
-        const int64_t i0 = t0 + (int64_t)tid * 8;
-        unsigned c[8];
-        unsigned sum = 0;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          c[k] = i0 + k < c1 ? cnt[i0 + k] : 0u;
-          sum += c[k];
-        }
+      for (int64_t t0 = c0; t0 < c1; t0 += B) {
+        const int64_t i = t0 + tid;
+        const int c = i < c1 ? (int)cnt[i] : 0;
         int tile;
-        unsigned at = run + (unsigned)block_scan((int)sum, &tile, wave_off);
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          if (i0 + k < c1) {
-            off[i0 + k] = at;
-            cnt[i0 + k] = at;  // scatter cursor
-          }
-          at += c[k];
+        const int o = block_scan(c, &tile, wave_off);
+        if (i < c1) {
+          off[i] = run + (unsigned)o;
+          cnt[i] = run + (unsigned)o;  // scatter cursor
         }
         run += (unsigned)tile;
       }
@@ -610,7 +599,7 @@ __global__ void k_bulk_find(int32_t* __restrict__ parent, const int2* __restrict
           const bool have = lo + (uint32_t)it < hi;
           const int2 pr = have ? sc.rd_pairs[lo + it] : make_int2(-1, -1);
           const bool go = have && pr.x == d.x;
-          if (go) st(parent + pr.y, d.y);
+          if (go && d.x != d.y) st(parent + pr.y, d.y);  // a root's own children already point at it
           mine += go;
           level_put(go, make_int2(pr.y, d.y), sc.rd_down, next, K, chunk, wave_off, flags);
         }
@@ -639,7 +628,7 @@ __global__ void k_bulk_find(int32_t* __restrict__ parent, const int2* __restrict
           const int64_t t = t0 + first;
           const int2 pr = t < hi ? sc.rd_pairs[t] : make_int2(-1, -1);
           const bool go = t < hi && pr.x == d.x;
-          if (go) st(parent + pr.y, d.y);
+          if (go && d.x != d.y) st(parent + pr.y, d.y);
           mine += go;
           level_put(go, make_int2(pr.y, d.y), sc.rd_down, next, K, chunk, wave_off, flags);
         }
