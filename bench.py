@@ -376,9 +376,11 @@ def rmat_unfiltered(s, opts, steps):
 
 def run_er(args):
     """The tiny uniform stream: n = 2^16, 16 minibatches of 2^14 uniform edges
-    (self-loops and repeats kept), each followed by 2^14 uniform query pairs;
-    plain launches.  Launch-latency bound: a pass is 32 operations of
-    2^14 items."""
+    (self-loops and repeats kept), each followed by 2^14 uniform query pairs.
+    Launch-latency bound: a pass is 32 operations of 2^14 items.  The value
+    is the plain form's; the pass replayed as one HIP graph and run as one
+    cooperative launch (cc_bulk_stream) are reported beside it, each checked
+    answer for answer against the plain launches."""
     import torch
 
     import synth
@@ -390,11 +392,13 @@ def run_er(args):
     opts = tuning.plain_options(s.n, workload="er")
     if args.options:
         opts.update(parse_options(args.options))
+    st = torch.cuda.Stream()  # capture needs a stream of its own
+    torch.cuda.set_stream(st)
     E = torch.from_numpy(s.edges).cuda()
     Q = torch.from_numpy(s.queries).cuda()
     out = torch.empty(Qn, dtype=torch.uint8, device="cuda")
     lab = torch.empty(s.n, dtype=torch.int32, device="cuda")
-    g = ccgpu.Graph(s.n, **opts)
+    g = ccgpu.Graph(s.n, stream=st, **opts)
     g.reserve(int(s.eoff[1] - s.eoff[0]))
     Es = [E[int(s.eoff[i]):int(s.eoff[i + 1])] for i in range(nb)]
     Qs = [Q[int(s.qoff[i]):int(s.qoff[i + 1])] for i in range(nb)]
@@ -408,22 +412,65 @@ def run_er(args):
         g.labels(out=lab)
         return g.num_components()
 
-    for _ in range(max(1, args.warmup)):
-        c = step()
+    def run(fn):
+        for _ in range(max(1, args.warmup)):
+            c = fn()
+        times = []
+        for _ in range(max(5, args.steps)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            c = fn()
+            times.append(time.perf_counter() - t0)
+        return sorted(times)[len(times) // 2], times, c
+
     steps = max(5, args.steps)
-    times = []
-    for _ in range(steps):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        c = step()
-        times.append(time.perf_counter() - t0)
+    med, times, c = run(step)
+    want = out.clone()
+    # the same pass replayed as one HIP graph, and as one cooperative launch
+    with g.capture() as cap:
+        g.reset()
+        for i in range(nb):
+            g.bulk_update(Es[i])
+            g.bulk_query(Qs[i], out=Os[i])
+        g.labels(out=lab)
+    rec = cap.recording
+
+    def replay():
+        rec.launch()
+        return g.num_components()
+
+    out.zero_()
+    med_graph, _, c2 = run(replay)
+    assert c2 == c and torch.equal(out, want), "replay differs from plain launches"
+    rec.close()
+    eo = torch.from_numpy(s.eoff.astype("int64")).cuda()
+    qo = torch.from_numpy(s.qoff.astype("int64")).cuda()
+    mx = int(max((s.eoff[1:] - s.eoff[:-1]).max(), (s.qoff[1:] - s.qoff[:-1]).max()))
+    stream_opts = tuning.lookup("stream", "er", s.n) or tuning.lookup("stream", "grid", 1 << 24) or {}
+    g.reset()
+    for k, v in stream_opts.items():
+        g.set_option(k, v)
+
+    def one_launch():
+        g.reset()
+        g.bulk_stream(E, eo, Q, qo, out, max_items=mx)
+        g.labels(out=lab)
+        return g.num_components()
+
+    out.zero_()
+    med_stream, _, c3 = run(one_launch)
+    assert c3 == c and torch.equal(out, want), "stream kernel differs from plain launches"
     assert g.sync() == 0
     g.close()
-    med = sorted(times)[len(times) // 2]
+    torch.cuda.set_stream(torch.cuda.default_stream())
     res = result((M + Qn) / med, steps, args.warmup, sum(times), {
         "workload": "er16-plain", "n": s.n, "edges": M, "minibatches": nb, "minibatch": 1 << 14,
         "queries_per_minibatch": 1 << 14, "form": "plain", "options": opts})
-    res.update({"median_ms_per_pass": med * 1e3, "components": c})
+    forms = {"plain": med, "hipgraph": med_graph, "stream_kernel": med_stream}
+    res.update({"median_ms_per_pass": med * 1e3, "components": c,
+                "forms": {k: {"value": (M + Qn) / v, "median_ms_per_pass": v * 1e3,
+                              "speedup_vs_plain": med / v} for k, v in forms.items()},
+                "stream_kernel_options": stream_opts})
     return res
 
 
@@ -901,8 +948,8 @@ def run_forms(args) -> dict:
     sub.steps, sub.warmup, sub.no_cpu_baseline, sub.options = max(3, min(args.steps, 5)), 1, True, ""
     forms = {}
     r = run_er(sub)
-    forms["er16"] = compact(r, ("median_ms_per_pass", "components", "config"))
-    log("forms: er16 %.3g items/s" % r["value"])
+    forms["er16"] = compact(r, ("median_ms_per_pass", "forms", "components", "config", "stream_kernel_options"))
+    log("forms: er16 %s" % {k: "%.3f ms" % v["median_ms_per_pass"] for k, v in r["forms"].items()})
     torch.cuda.empty_cache()
     r = run_grid(sub)
     forms["grid4096"] = compact(r, ("forms", "speedup_vs_plain", "components", "config"))

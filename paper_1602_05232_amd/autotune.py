@@ -15,6 +15,7 @@ linking in place) on top of the stage-one winner.
   python -m paper_1602_05232_amd.autotune --workload rmat24
   python -m paper_1602_05232_amd.autotune --workload rmat24-unfiltered
   python -m paper_1602_05232_amd.autotune --workload er16
+  python -m paper_1602_05232_amd.autotune --workload er16-stream
   python -m paper_1602_05232_amd.autotune --workload grid4096
   python -m paper_1602_05232_amd.autotune --workload grid4096-stream
   python -m paper_1602_05232_amd.autotune --workload batched1024
@@ -226,8 +227,8 @@ def tune_serve(trace, n, reps=3, quick=False, log=print):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="rmat24",
-                    choices=["rmat24", "rmat24-unfiltered", "er16", "grid4096", "grid4096-stream", "batched1024",
-                             "serve64"])
+                    choices=["rmat24", "rmat24-unfiltered", "er16", "er16-stream", "grid4096", "grid4096-stream",
+                             "batched1024", "serve64"])
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--quick", action="store_true")
     ap.add_argument("--log", default="", help="also write every candidate's time to this file")
@@ -253,6 +254,10 @@ def main():
         s = synth.er_stream()
         t, opts = tune_plain(s, "er", args.reps, args.quick, log=log)
         tuning.store("plain", "er", s.n, opts)
+    elif w == "er16-stream":
+        s = synth.er_stream()
+        t, opts = tune_stream(s, args.reps, log=log)
+        tuning.store("stream", "er", s.n, opts)
     elif w == "grid4096":
         s = synth.grid_stream_cfg()
         t, opts = tune_plain(s, "grid", args.reps, args.quick, filtered=False, log=log)
