@@ -56,7 +56,16 @@ int cc_pool_set_stream(cc_pool* p, void* stream);
  * CC_OPT_ITEMS, CC_OPT_QUERY_HALVING, CC_OPT_HOOK 0, 1 or 2 (set before
  * adding graphs, CC_EINVAL once a graph exists; under 2, union by rank,
  * cc_pool_add refuses graphs of more than 2^27 vertices), CC_OPT_GRID_CAP,
- * CC_OPT_COMPRESS_LINKED, CC_OPT_SPIN_LIMIT, CC_OPT_ONE_LAUNCH. */
+ * CC_OPT_COMPRESS_LINKED, CC_OPT_SPIN_LIMIT, CC_OPT_ONE_LAUNCH, and
+ * CC_OPT_FILTER 0 or 1 (any other value: CC_EINVAL).  CC_OPT_FILTER 1 is a
+ * membership filter per graph (an anchor vertex and one bit per slot of the
+ * arena, capacity / 8 bytes, allocated when first turned on; CC_ENOMEM if
+ * that fails): before an update round on a graph updated since, one pass
+ * over the graph's slots marks the vertices known to be connected to the
+ * anchor, and an edge or query pair with both ends marked is settled
+ * without a parent read.  The one-launch form reads the marks but does not
+ * renew them.  Turning it on clears every mark; reset, reset_all, add and
+ * load clear the graph's own.  No option changes a result. */
 int cc_pool_set_option(cc_pool* p, int key, int64_t value);
 
 /* Add a graph on vertices [0, n), every vertex alone; *id receives its

@@ -152,6 +152,13 @@ def pool_candidates(quick=False):
     # wins above: union by rank without linked-root compression
     out += [dict(block=b, items=i, hook=2, compress_linked=0, grid_cap=g)
             for b, i, g in itertools.product((256, 512, 1024), (0, 4), (1024, 2048, 8192))]
+    # the membership filter (bits refreshed before each update round) on the
+    # same family, and under hashed priority
+    out += [dict(block=b, items=i, hook=2, compress_linked=0, filter=1)
+            for b, i in itertools.product((256, 512, 1024), (0, 4, 8))]
+    out += [dict(block=b, items=0, hook=1, compress_linked=0, filter=1) for b in (256, 512, 1024)]
+    out += [dict(block=b, items=0, hook=2, compress_linked=0, filter=1, grid_cap=g)
+            for b, g in itertools.product((256, 512), (1024, 2048, 8192))]
     return out[::5] if quick else out
 
 

@@ -146,15 +146,24 @@ inline bool get_tuning(const Tuning* t, int key, int64_t* v) {
 }
 
 // Upper bound on the blocks of a cooperative launch (every block resident
-// at once): the occupancy calculator's blocks per compute unit times the
-// units.  Measured on an idle device, grids of that size became resident at
-// once for every register footprint tried (the calculator is conservative
-// above 62 VGPRs); what can keep a grid from becoming resident is another
-// cooperative grid holding compute units, which coop_before/coop_after rule
-// out for this library's launches.  A grid that still cannot become
-// resident ends at the barrier's spin limit with CC_EDEVICE.
-inline int64_t coop_limit(int per_cu, int cus) {
-  return (int64_t)(per_cu > 0 ? per_cu : 1) * cus;
+// at once): the occupancy calculator's blocks per compute unit, but at most
+// kCoopWavesPerCu wavefronts per unit, times the units.  Two kernels for which
+// the calculator allowed 8 wavefronts per SIMD (its maximum; both with an
+// SGPR allocation of 96) did not become resident at that size on an idle
+// device: the contracting update, 2048 blocks of 256 (1792 resident, 7 per
+// unit), and the pool's one-launch form with 4 items per thread, 1024 blocks
+// of 512 (2.7 s per launch instead of 3 ms: the blocks left out ran only as
+// the spinning ones were preempted).  Grids of at most 7 wavefronts per SIMD
+// have always become resident.  Cooperative grids of this library also
+// never overlap (coop_before/coop_after), and a grid that still cannot
+// become resident ends at the barrier's spin limit with CC_EDEVICE.
+constexpr int kCoopWavesPerCu = 28;  // 7 per SIMD, 4 SIMDs
+
+inline int64_t coop_limit(int per_cu, int cus, int block) {
+  const int waves = (block + 63) / 64;
+  int b = kCoopWavesPerCu / (waves > 0 ? waves : 1);
+  if (per_cu < b) b = per_cu;
+  return (int64_t)(b > 0 ? b : 1) * cus;
 }
 
 // Cooperative launches of this library never overlap on a device.  Each

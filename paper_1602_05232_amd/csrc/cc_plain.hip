@@ -433,7 +433,7 @@ int launch_bulk_find_t(cc_graph* g, const int2* items, int64_t count, uint8_t* o
   HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bulk_find<KIND, Ord, PH2>, block, 0));
   HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device));
   int64_t grid = (2 * count + block - 1) / block;
-  grid = std::min<int64_t>(std::min<int64_t>(grid, cc::coop_limit(per_cu, cus)), 1024);
+  grid = std::min<int64_t>(std::min<int64_t>(grid, cc::coop_limit(per_cu, cus, block)), 1024);
   grid = std::max<int64_t>(1, std::min<int64_t>(grid, (int64_t)g->tune.grid_cap));
   // level 0 takes one segment per block of the 2 * count endpoints
   const int64_t seg0_cap = (2 * count + grid - 1) / grid;
@@ -488,7 +488,7 @@ int contract_grid(cc_graph* g, int64_t m, int64_t* grid) {
   HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_contract<Ord>, block, 0));
   HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device));
   int64_t b = (m + 4 * block - 1) / (4 * block);
-  b = std::min<int64_t>(b, cc::coop_limit(per_cu, cus));
+  b = std::min<int64_t>(b, cc::coop_limit(per_cu, cus, block));
   b = std::min<int64_t>(b, (int64_t)g->tune.grid_cap);
   *grid = std::max<int64_t>(b, 1);
   return CC_OK;
@@ -1205,7 +1205,7 @@ int launch_stream(cc_graph* g, int64_t batches, const int32_t* edges, const int6
   HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_stream<Ord>, block, 0));
   HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device));
   int64_t grid = (max_items + block - 1) / block;
-  grid = std::min<int64_t>(grid, cc::coop_limit(per_cu, cus));
+  grid = std::min<int64_t>(grid, cc::coop_limit(per_cu, cus, block));
   grid = std::min<int64_t>(grid, std::min<int64_t>(1024, (int64_t)g->tune.grid_cap));
   grid = std::max<int64_t>(grid, 1);
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, g->stream, g->gbar, kBarWords);

@@ -70,6 +70,10 @@ struct cc_pool {
   int2* table = nullptr;                // (base, n) of the graphs in use, for cc_pool_reset_all
   std::vector<int2> table_host;
   bool table_stale = true;              // graphs added or removed since the table was uploaded
+  uint32_t* member = nullptr;           // membership filter: one bit per arena slot (+1 word)
+  int32_t* anchors = nullptr;           // membership filter: anchor vertex per graph handle, -1 for none,
+                                        // then (aroot) the anchor's root at the last refresh, -1 for no bits
+  std::vector<uint8_t> stale;           // membership filter: graph updated since its bits were last refreshed
   RingSlot ring[kRing];
   int ring_next = 0;
   cc::Tuning tune;
@@ -164,13 +168,13 @@ int reserve_meta(RingSlot* s, int64_t words) {
   return CC_OK;
 }
 
-template <int ITEMS, int HOOK, bool HALVE>
-int launch_rounds_t(cc_pool* p, const RingSlot* s, int rounds, uint32_t max_tiles) {
+template <int ITEMS, int HOOK, bool HALVE, bool FILT>
+int launch_rounds_t(cc_pool* p, const RingSlot* s, int rounds, uint32_t max_tiles, const OpDesc* fops) {
   const int B = p->tune.block;
   int per_cu = 0, cus = 0;
-  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pool_rounds<ITEMS, HOOK, HALVE>, B, 0));
+  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pool_rounds<ITEMS, HOOK, HALVE, FILT>, B, 0));
   HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device));
-  int64_t grid = std::min<int64_t>(std::min<int64_t>(max_tiles, cc::coop_limit(per_cu, cus)), p->tune.grid_cap);
+  int64_t grid = std::min<int64_t>(std::min<int64_t>(max_tiles, cc::coop_limit(per_cu, cus, B)), p->tune.grid_cap);
   grid = std::max<int64_t>(grid, 1);
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, p->stream, s->bar, kBarWords);
   HIP_TRY(hipGetLastError());
@@ -182,54 +186,108 @@ int launch_rounds_t(cc_pool* p, const RingSlot* s, int rounds, uint32_t max_tile
   int* flags = p->flags;
   unsigned* bar = s->bar;
   unsigned spin = (unsigned)p->tune.spin_limit;
-  void* args[] = {&ops, &rstart, &rtiles, &rounds, &arena, &glinks, &flags, &bar, &spin};
+  uint32_t* member = p->member;
+  int32_t* anchors = p->anchors;
+  int32_t* aroot = p->anchors ? p->anchors + p->max_graphs : nullptr;
+  // refresh table after the round table: starts (rounds + 1), then tiles
+  const int32_t* fstart = s->meta_dev + 2 * rounds + 1;
+  const uint32_t* ftiles = reinterpret_cast<const uint32_t*>(s->meta_dev + 3 * rounds + 2);
+  void* args[] = {&ops,    &rstart,  &rtiles, &rounds, &arena, &glinks, &flags,  &bar,
+                  &spin,   &member,  &anchors, &aroot, &fops,  &fstart, &ftiles};
   if (const int crc = cc::coop_before(p->stream)) return crc;
-  HIP_TRY(hipLaunchCooperativeKernel((const void*)k_pool_rounds<ITEMS, HOOK, HALVE>, dim3((unsigned)grid), dim3(B),
-                                     args, 0, p->stream));
+  HIP_TRY(hipLaunchCooperativeKernel((const void*)k_pool_rounds<ITEMS, HOOK, HALVE, FILT>, dim3((unsigned)grid),
+                                     dim3(B), args, 0, p->stream));
   if (const int crc = cc::coop_after(p->stream)) return crc;
   return CC_OK;
 }
 
+template <int ITEMS, int HOOK, bool FILT>
+int launch_rounds_f(cc_pool* p, const RingSlot* s, int rounds, uint32_t max_tiles, const OpDesc* fops) {
+  return p->tune.query_halving ? launch_rounds_t<ITEMS, HOOK, true, FILT>(p, s, rounds, max_tiles, fops)
+                               : launch_rounds_t<ITEMS, HOOK, false, FILT>(p, s, rounds, max_tiles, fops);
+}
+
 template <int ITEMS, int HOOK>
-int launch_rounds_h(cc_pool* p, const RingSlot* s, int rounds, uint32_t max_tiles) {
-  return p->tune.query_halving ? launch_rounds_t<ITEMS, HOOK, true>(p, s, rounds, max_tiles)
-                               : launch_rounds_t<ITEMS, HOOK, false>(p, s, rounds, max_tiles);
+int launch_rounds_h(cc_pool* p, const RingSlot* s, int rounds, uint32_t max_tiles, const OpDesc* fops) {
+  return p->tune.filter && p->member ? launch_rounds_f<ITEMS, HOOK, true>(p, s, rounds, max_tiles, fops)
+                                     : launch_rounds_f<ITEMS, HOOK, false>(p, s, rounds, max_tiles, fops);
 }
 
 template <int ITEMS>
-int launch_rounds_i(cc_pool* p, const RingSlot* s, int rounds, uint32_t max_tiles) {
+int launch_rounds_i(cc_pool* p, const RingSlot* s, int rounds, uint32_t max_tiles, const OpDesc* fops) {
   switch (p->tune.hook) {
-    case 1: return launch_rounds_h<ITEMS, 1>(p, s, rounds, max_tiles);
-    case 2: return launch_rounds_h<ITEMS, 2>(p, s, rounds, max_tiles);
-    default: return launch_rounds_h<ITEMS, 0>(p, s, rounds, max_tiles);
+    case 1: return launch_rounds_h<ITEMS, 1>(p, s, rounds, max_tiles, fops);
+    case 2: return launch_rounds_h<ITEMS, 2>(p, s, rounds, max_tiles, fops);
+    default: return launch_rounds_h<ITEMS, 0>(p, s, rounds, max_tiles, fops);
   }
 }
 
-int launch_rounds(cc_pool* p, const RingSlot* s, int items, int rounds, uint32_t max_tiles) {
+// fops: the run's refresh descriptors (membership filter)
+int launch_rounds(cc_pool* p, const RingSlot* s, int items, int rounds, uint32_t max_tiles, const OpDesc* fops) {
   switch (items) {
-    case 1: return launch_rounds_i<1>(p, s, rounds, max_tiles);
-    case 2: return launch_rounds_i<2>(p, s, rounds, max_tiles);
-    case 8: return launch_rounds_i<8>(p, s, rounds, max_tiles);
-    default: return launch_rounds_i<4>(p, s, rounds, max_tiles);
+    case 1: return launch_rounds_i<1>(p, s, rounds, max_tiles, fops);
+    case 2: return launch_rounds_i<2>(p, s, rounds, max_tiles, fops);
+    case 8: return launch_rounds_i<8>(p, s, rounds, max_tiles, fops);
+    default: return launch_rounds_i<4>(p, s, rounds, max_tiles, fops);
   }
 }
 
-template <int ITEMS, int HOOK, bool RECORD>
+template <int ITEMS, int HOOK, bool RECORD, bool FILT>
 void launch_phase_t(cc_pool* p, const RingSlot* s, const OpDesc* d, int nops, uint32_t ntiles) {
   const int B = p->tune.block;
   const unsigned grid = (unsigned)std::min<int64_t>(ntiles, p->tune.grid_cap);
+  const int32_t* aroot = p->anchors ? p->anchors + p->max_graphs : nullptr;
   if (p->tune.query_halving)
-    hipLaunchKernelGGL((k_pool_phase<ITEMS, HOOK, RECORD, true>), dim3(grid), dim3(B), 0, p->stream, d, nops,
-                       ntiles, p->arena, p->glinks, p->flags, s->hooked, s->ctl);
+    hipLaunchKernelGGL((k_pool_phase<ITEMS, HOOK, RECORD, true, FILT>), dim3(grid), dim3(B), 0, p->stream, d, nops,
+                       ntiles, p->arena, p->glinks, p->flags, s->hooked, s->ctl, p->member, aroot);
   else
-    hipLaunchKernelGGL((k_pool_phase<ITEMS, HOOK, RECORD, false>), dim3(grid), dim3(B), 0, p->stream, d, nops,
-                       ntiles, p->arena, p->glinks, p->flags, s->hooked, s->ctl);
+    hipLaunchKernelGGL((k_pool_phase<ITEMS, HOOK, RECORD, false, FILT>), dim3(grid), dim3(B), 0, p->stream, d, nops,
+                       ntiles, p->arena, p->glinks, p->flags, s->hooked, s->ctl, p->member, aroot);
+}
+
+template <int ITEMS, int HOOK, bool FILT>
+void launch_phase_f(cc_pool* p, const RingSlot* s, const OpDesc* d, int nops, uint32_t ntiles, bool record) {
+  if (record) launch_phase_t<ITEMS, HOOK, true, FILT>(p, s, d, nops, ntiles);
+  else launch_phase_t<ITEMS, HOOK, false, FILT>(p, s, d, nops, ntiles);
 }
 
 template <int ITEMS, int HOOK>
 void launch_phase_h(cc_pool* p, const RingSlot* s, const OpDesc* d, int nops, uint32_t ntiles, bool record) {
-  if (record) launch_phase_t<ITEMS, HOOK, true>(p, s, d, nops, ntiles);
-  else launch_phase_t<ITEMS, HOOK, false>(p, s, d, nops, ntiles);
+  if (p->tune.filter && p->member) launch_phase_f<ITEMS, HOOK, true>(p, s, d, nops, ntiles, record);
+  else launch_phase_f<ITEMS, HOOK, false>(p, s, d, nops, ntiles, record);
+}
+
+// Membership filter: clear the bits of arena slots [base, base + n) and the
+// anchors of handles [g0, g1) (no-op while the filter is off; turning it on
+// clears everything).
+int filter_clear(cc_pool* p, int64_t base, int64_t n, int32_t g0, int32_t g1) {
+  if (!p->tune.filter || !p->member) return CC_OK;
+  const int64_t work = std::max<int64_t>((n + 31) / 32 + 1, g1 - g0);
+  hipLaunchKernelGGL(k_pool_filter_clear, dim3(blocks_for(work, 256, 4096)), dim3(256), 0, p->stream, p->member,
+                     base, n, p->anchors, p->anchors + p->max_graphs, g0, g1);
+  HIP_TRY(hipGetLastError());
+  for (int32_t g = g0; g < g1; ++g) p->stale[(size_t)g] = 0;
+  return CC_OK;
+}
+
+constexpr int kRefreshBlock = 256;  // bitmap words per refresh tile
+
+// Before an update round: anchor roots, then the refresh pass, for the
+// graphs listed in d (nops descriptors with word-tile offsets).
+void filter_refresh(cc_pool* p, const OpDesc* d, int nops, uint32_t ntiles) {
+  int32_t* aroot = p->anchors + p->max_graphs;
+  const unsigned tiles = (unsigned)std::min<int64_t>(ntiles, 8192);
+  if (p->tune.hook == 2) {
+    hipLaunchKernelGGL(k_pool_filter_roots<true>, dim3((nops + 255) / 256), dim3(256), 0, p->stream, d, nops,
+                       p->arena, p->anchors, aroot, p->flags);
+    hipLaunchKernelGGL(k_pool_filter_refresh<true>, dim3(tiles), dim3(kRefreshBlock), 0, p->stream, d, nops, ntiles,
+                       p->arena, p->member, aroot);
+  } else {
+    hipLaunchKernelGGL(k_pool_filter_roots<false>, dim3((nops + 255) / 256), dim3(256), 0, p->stream, d, nops,
+                       p->arena, p->anchors, aroot, p->flags);
+    hipLaunchKernelGGL(k_pool_filter_refresh<false>, dim3(tiles), dim3(kRefreshBlock), 0, p->stream, d, nops, ntiles,
+                       p->arena, p->member, aroot);
+  }
 }
 
 template <int ITEMS>
@@ -263,6 +321,7 @@ extern "C" cc_pool* cc_pool_create(int64_t capacity, int32_t max_graphs) {
   p->capacity = capacity;
   p->max_graphs = max_graphs;
   p->graphs.resize((size_t)max_graphs);
+  p->stale.assign((size_t)max_graphs, 0);
   p->gaps[0] = capacity;
   auto fail = [&](const char* what) -> cc_pool* {
     cc_set_error("cc_pool_create: %s failed", what);
@@ -308,6 +367,8 @@ extern "C" int cc_pool_destroy(cc_pool* p) {
   (void)hipFree(p->staging);
   (void)hipFree(p->check);
   (void)hipFree(p->table);
+  (void)hipFree(p->member);
+  (void)hipFree(p->anchors);
   delete p;
   return CC_OK;
 }
@@ -320,8 +381,8 @@ extern "C" int cc_pool_set_stream(cc_pool* p, void* stream) {
 
 extern "C" int cc_pool_set_option(cc_pool* p, int key, int64_t value) {
   if (!p) return CC_EINVAL;
-  if (key == CC_OPT_UPDATE_MODE || key == CC_OPT_COMPRESS_EVERY || key == CC_OPT_FIND || key == CC_OPT_FILTER ||
-      key == CC_OPT_QUERY_ITEMS || key == CC_OPT_SPLIT_BELOW) {
+  if (key == CC_OPT_UPDATE_MODE || key == CC_OPT_COMPRESS_EVERY || key == CC_OPT_FIND || key == CC_OPT_QUERY_ITEMS ||
+      key == CC_OPT_SPLIT_BELOW) {
     cc_set_error("cc_pool_set_option: option %d does not apply to pools", key);
     return CC_EINVAL;
   }
@@ -331,6 +392,33 @@ extern "C" int cc_pool_set_option(cc_pool* p, int key, int64_t value) {
         cc_set_error("cc_pool_set_option: the linking order is fixed once a graph exists");
         return CC_EINVAL;
       }
+  }
+  if (key == CC_OPT_FILTER) {
+    if (value != 0 && value != 1) {
+      cc_set_error("cc_pool_set_option: the pool's filter is 0 (off) or 1 (on), not %lld", (long long)value);
+      return CC_EINVAL;
+    }
+    if (value == 1 && !p->tune.filter) {
+      DeviceGuard dg(p->device);
+      const int64_t words = p->capacity / 32 + 1;
+      if (!p->member && hipMalloc((void**)&p->member, (size_t)words * 4) != hipSuccess) {
+        p->member = nullptr;
+        cc_set_error("cc_pool_set_option: membership bitmap allocation failed");
+        return CC_ENOMEM;
+      }
+      if (!p->anchors && hipMalloc((void**)&p->anchors, (size_t)p->max_graphs * 8) != hipSuccess) {
+        p->anchors = nullptr;
+        cc_set_error("cc_pool_set_option: anchor table allocation failed");
+        return CC_ENOMEM;
+      }
+      p->tune.filter = 1;
+      // bits kept while the filter was off may describe forests since reset
+      if (const int rc = filter_clear(p, 0, p->capacity, 0, p->max_graphs)) return rc;
+      for (int32_t g = 0; g < p->max_graphs; ++g) p->stale[(size_t)g] = p->graphs[(size_t)g].used ? 1 : 0;
+      return CC_OK;
+    }
+    p->tune.filter = (int)value;
+    return CC_OK;
   }
   if (!cc::set_tuning(&p->tune, key, value)) {
     cc_set_error("cc_pool_set_option: key %d value %lld rejected", key, (long long)value);
@@ -370,6 +458,7 @@ extern "C" int cc_pool_add(cc_pool* p, int64_t n, int32_t* id) {
                      (int32_t)base, (int32_t)n);
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, p->stream, p->glinks + (size_t)slot * kPoolLinkStride, 1);
   HIP_TRY(hipGetLastError());
+  if (const int rc = filter_clear(p, base, n, slot, slot + 1)) return rc;
   *id = slot;
   return CC_OK;
 }
@@ -391,7 +480,7 @@ extern "C" int cc_pool_reset(cc_pool* p, int32_t id) {
                      (int32_t)g.base, (int32_t)g.n);
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, p->stream, p->glinks + (size_t)id * kPoolLinkStride, 1);
   HIP_TRY(hipGetLastError());
-  return CC_OK;
+  return filter_clear(p, g.base, g.n, id, id + 1);
 }
 
 extern "C" int cc_pool_reset_all(cc_pool* p) {
@@ -417,7 +506,7 @@ extern "C" int cc_pool_reset_all(cc_pool* p) {
   }
   hipLaunchKernelGGL(k_zero_u64, dim3(64), dim3(256), 0, p->stream, p->glinks, p->max_graphs * kPoolLinkStride);
   HIP_TRY(hipGetLastError());
-  return CC_OK;
+  return filter_clear(p, 0, p->capacity, 0, p->max_graphs);
 }
 
 extern "C" int64_t cc_pool_graph_vertices(const cc_pool* p, int32_t id) {
@@ -478,8 +567,10 @@ extern "C" int cc_pool_run(cc_pool* p, const cc_op* ops, int32_t num_ops) {
   bool any_update = false;
   for (int32_t i = 0; i < num_ops; ++i) any_update |= ops[i].kind == 0 && ops[i].count > 0;
   const bool one_launch = p->tune.one_launch != 0;
+  const bool filt = p->tune.filter != 0 && p->member != nullptr;
   RingSlot* slot = nullptr;
-  int rc = reserve_slot(p, live, any_update && p->tune.compress_linked && !one_launch, one_launch, &slot);
+  int rc = reserve_slot(p, filt ? 2 * live : live, any_update && p->tune.compress_linked && !one_launch, one_launch,
+                        &slot);
   if (rc != CC_OK) return rc;
   const int B = p->tune.block;
   // lay the descriptors out round by round; each round gets its own items per thread
@@ -523,25 +614,59 @@ extern "C" int cc_pool_run(cc_pool* p, const cc_op* ops, int32_t num_ops) {
     }
     rtiles[(size_t)r] += (uint32_t)nt;
   }
-  HIP_TRY(hipMemcpyAsync(slot->dev, slot->host, (size_t)live * sizeof(OpDesc), hipMemcpyHostToDevice, p->stream));
+  // membership filter: refresh descriptors (after the `live` round
+  // descriptors) for the update operations of each round whose graph changed
+  // since its bits were last refreshed; the one-launch form only reads bits
+  std::vector<int64_t> fstart((size_t)rounds, live), fcount((size_t)rounds, 0);
+  std::vector<uint32_t> ftiles((size_t)rounds, 0);
+  int64_t nref = 0;
+  if (filt) {
+    const int64_t words_per_tile = one_launch ? B : kRefreshBlock;  // the refresh's block width
+    for (int r = 0; r < rounds; ++r) {
+      fstart[(size_t)r] = live + nref;
+      for (int64_t i = rstart[(size_t)r]; i < rstart[(size_t)r + 1]; ++i) {
+        const OpDesc& d = slot->host[i];
+        if (d.kind != 0 || !p->stale[(size_t)d.graph]) continue;
+        OpDesc& f = slot->host[live + nref++];
+        f = d;
+        f.tile0 = ftiles[(size_t)r];
+        const int64_t words = (((int64_t)d.base + d.n - 1) >> 5) - ((int64_t)d.base >> 5) + 1;
+        ftiles[(size_t)r] += (uint32_t)((words + words_per_tile - 1) / words_per_tile);  // at most 2^26 in all
+        fcount[(size_t)r]++;
+      }
+      for (int64_t i = rstart[(size_t)r]; i < rstart[(size_t)r + 1]; ++i)
+        if (slot->host[i].kind == 0) p->stale[(size_t)slot->host[i].graph] = 1;
+    }
+  }
+  HIP_TRY(hipMemcpyAsync(slot->dev, slot->host, (size_t)(live + nref) * sizeof(OpDesc), hipMemcpyHostToDevice,
+                         p->stream));
   if (one_launch) {
     // compact the non-empty rounds into the round table: starts, then tiles
     std::vector<int> used;
     for (int r = 0; r < rounds; ++r)
       if (rcount[(size_t)r] > 0) used.push_back(r);
     const int nr = (int)used.size();
-    rc = reserve_meta(slot, 2 * (int64_t)nr + 1);
+    rc = reserve_meta(slot, 4 * (int64_t)nr + 2);
     if (rc != CC_OK) return rc;
     uint32_t max_tiles = 1;
+    // round table: starts (nr + 1), tiles (nr); then the refresh table:
+    // starts relative to the first refresh descriptor (nr + 1), tiles (nr)
+    int32_t* fs = slot->meta_host + 2 * nr + 1;
+    int32_t* ft = slot->meta_host + 3 * nr + 2;
     for (int k = 0; k < nr; ++k) {
-      slot->meta_host[k] = (int32_t)rstart[(size_t)used[(size_t)k]];
-      slot->meta_host[nr + 1 + k] = (int32_t)rtiles[(size_t)used[(size_t)k]];
-      max_tiles = std::max(max_tiles, rtiles[(size_t)used[(size_t)k]]);
+      const size_t r = (size_t)used[(size_t)k];
+      slot->meta_host[k] = (int32_t)rstart[r];
+      slot->meta_host[nr + 1 + k] = (int32_t)rtiles[r];
+      max_tiles = std::max(max_tiles, rtiles[r]);
+      fs[k] = (int32_t)(fstart[r] - live);
+      ft[k] = (int32_t)ftiles[r];
+      max_tiles = std::max(max_tiles, ftiles[r]);
     }
     slot->meta_host[nr] = (int32_t)(rstart[(size_t)used[(size_t)nr - 1]] + rcount[(size_t)used[(size_t)nr - 1]]);
-    HIP_TRY(hipMemcpyAsync(slot->meta_dev, slot->meta_host, (size_t)(2 * nr + 1) * 4, hipMemcpyHostToDevice,
+    fs[nr] = (int32_t)(fstart[(size_t)used[(size_t)nr - 1]] - live + fcount[(size_t)used[(size_t)nr - 1]]);
+    HIP_TRY(hipMemcpyAsync(slot->meta_dev, slot->meta_host, (size_t)(4 * nr + 2) * 4, hipMemcpyHostToDevice,
                            p->stream));
-    rc = launch_rounds(p, slot, ritem_per_thread[0], nr, max_tiles);
+    rc = launch_rounds(p, slot, ritem_per_thread[0], nr, max_tiles, slot->dev + live);
     if (rc != CC_OK) return rc;
     HIP_TRY(hipEventRecord(slot->done, p->stream));
     slot->pending = true;
@@ -549,6 +674,8 @@ extern "C" int cc_pool_run(cc_pool* p, const cc_op* ops, int32_t num_ops) {
   }
   for (int r = 0; r < rounds; ++r) {
     if (rcount[(size_t)r] == 0) continue;
+    if (fcount[(size_t)r] > 0)
+      filter_refresh(p, slot->dev + fstart[(size_t)r], (int)fcount[(size_t)r], ftiles[(size_t)r]);
     const bool record = rupd[(size_t)r] && p->tune.compress_linked;
     launch_phase(p, slot, ritem_per_thread[(size_t)r], slot->dev + rstart[(size_t)r], (int)rcount[(size_t)r],
                  rtiles[(size_t)r], record);
@@ -718,6 +845,8 @@ extern "C" int cc_pool_load(cc_pool* p, int32_t id, const void* host_buf) {
   unsigned long long links = (unsigned long long)hdr[1];
   HIP_TRY(hipMemcpyAsync(p->arena + g.base, p->staging, (size_t)g.n * 4, hipMemcpyDeviceToDevice, p->stream));
   HIP_TRY(hipMemcpyAsync(p->glinks + (size_t)id * kPoolLinkStride, &links, 8, hipMemcpyHostToDevice, p->stream));
+  if (const int frc = filter_clear(p, g.base, g.n, id, id + 1)) return frc;
+  p->stale[(size_t)id] = 1;
   HIP_TRY(hipStreamSynchronize(p->stream));
   return CC_OK;
 }

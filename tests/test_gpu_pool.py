@@ -33,7 +33,11 @@ def small_graphs(G, seed=5):
                                   dict(items=8, block=512, compress_linked=0, query_halving=0),
                                   dict(one_launch=1), dict(one_launch=1, hook=1, items=1, grid_cap=3),
                                   dict(hook=2), dict(hook=2, compress_linked=0, items=8, block=1024),
-                                  dict(one_launch=1, hook=2, grid_cap=7)],
+                                  dict(one_launch=1, hook=2, grid_cap=7),
+                                  dict(filter=1), dict(filter=1, hook=2, compress_linked=0, items=8, block=512),
+                                  dict(filter=1, hook=1, items=1, block=64, grid_cap=5),
+                                  dict(filter=1, hook=0, items=4, query_halving=0),
+                                  dict(filter=1, one_launch=1, hook=2, grid_cap=7)],
                          ids=lambda o: ",".join("%s=%s" % kv for kv in sorted(o.items())) or "default")
 def test_pool_steps_match_oracle(cc, opts):
     G = 96
@@ -261,4 +265,108 @@ def test_overlapping_one_launch_runs_on_two_streams(cc):
         np.testing.assert_array_equal(outs[g].cpu().numpy(), np.concatenate(want), err_msg="graph %d" % g)
         np.testing.assert_array_equal(pool.labels(ids[g]).cpu().numpy(), ref.labels(), err_msg="graph %d" % g)
     assert pool.sync() == cc.cc.CC_OK
+    pool.close()
+
+
+@pytest.mark.parametrize("hook", [0, 2])
+def test_pool_filter_cleared_with_the_forest(cc, hook):
+    """The pool's membership bits claim connectivity to an anchor; every
+    operation that replaces a graph's forest (reset, reset_all, remove and
+    add over the same range, load, turning the filter back on) must drop
+    them, or a query would answer 1 for vertices the new forest keeps apart."""
+    n = 4000
+    pool = cc.Pool(2 * n + 100, 4, hook=hook, filter=1)
+    a = pool.add(n)
+    b = pool.add(n)
+    ring = np.stack([np.arange(n), (np.arange(n) + 1) % n], axis=1).astype(np.int32)  # one component
+    sparse = synth.uniform_pairs(synth.key(71, 0, 1), 0, n // 4, n)
+    q = synth.uniform_pairs(synth.key(71, 0, 2), 0, 3000, n)
+    out = torch.empty(len(q), dtype=torch.uint8, device="cuda")
+
+    def ask(g):
+        pool.run([(g, cc.QUERY, dev(q), out)])
+        return out.cpu().numpy().copy()
+
+    def fill(g):
+        # twice, so that the second pass finds the tree joined and sets bits
+        pool.run([(g, cc.UPDATE, dev(ring), None)])
+        pool.run([(g, cc.UPDATE, dev(ring), None)])
+        assert ask(g).all()
+
+    ref = oracle.UnionFind(n)
+    ref.bulk_update(sparse)
+    want_sparse = ref.bulk_query(q)
+    want_alone = (q[:, 0] == q[:, 1]).astype(np.uint8)
+    pool.run([(b, cc.UPDATE, dev(sparse), None)])
+    img = pool.save(b)
+    # reset
+    fill(a)
+    pool.reset(a)
+    np.testing.assert_array_equal(ask(a), want_alone)
+    # reset_all
+    fill(a)
+    pool.reset_all()
+    np.testing.assert_array_equal(ask(a), want_alone)
+    # load over a filled graph
+    fill(a)
+    pool.load(a, img)
+    np.testing.assert_array_equal(ask(a), want_sparse)
+    pool.run([(a, cc.UPDATE, dev(sparse), None)])
+    np.testing.assert_array_equal(ask(a), want_sparse)
+    # remove, then a new graph over the same slots
+    fill(a)
+    pool.remove(a)
+    c = pool.add(n)
+    np.testing.assert_array_equal(ask(c), want_alone)
+    # bits left from before the filter was turned off
+    fill(c)
+    pool.set_option("filter", 0)
+    pool.reset(c)
+    pool.set_option("filter", 1)
+    np.testing.assert_array_equal(ask(c), want_alone)
+    pool.run([(c, cc.UPDATE, dev(sparse), None)])
+    np.testing.assert_array_equal(ask(c), want_sparse)
+    assert pool.sync() == cc.cc.CC_OK
+    with pytest.raises(cc.CCError) as ei:
+        pool.set_option("filter", 2)
+    assert ei.value.code == cc.cc.CC_EINVAL
+    pool.close()
+
+
+@pytest.mark.parametrize("items", [2, 4, 8])
+def test_one_launch_full_grid_is_resident(cc, items):
+    """The one-launch form over many more tiles than the grid holds, with the
+    small register footprints of 2 and 4 items per thread: the cooperative
+    grid must become resident at once (a grid sized to the occupancy
+    calculator's 8 wavefronts per SIMD took seconds per launch), and every
+    answer equals the oracle's."""
+    import time
+    G, n = 64, 1 << 14
+    ks = [synth.key(83, g, 1) for g in range(G)]
+    E = [synth.uniform_pairs(k, 0, 8 * n, n) for k in ks]
+    Qh = [synth.uniform_pairs(k, 8 * n, 512, n) for k in ks]
+    pool = cc.Pool(G * n, G, one_launch=1, hook=2, compress_linked=0, block=512, items=items)
+    ids = [pool.add(n) for _ in range(G)]
+    Ed = [dev(e) for e in E]
+    Qd = [dev(q) for q in Qh]
+    outs = [torch.zeros(len(q), dtype=torch.uint8, device="cuda") for q in Qh]
+    ops = [(ids[g], cc.UPDATE, Ed[g][: 4 * n], None) for g in range(G)]
+    ops += [(ids[g], cc.UPDATE, Ed[g][4 * n:], None) for g in range(G)]
+    ops += [(ids[g], cc.QUERY, Qd[g], outs[g]) for g in range(G)]
+    prep = pool.prepare(ops)
+    pool.run(prep)  # first launch: module load and allocations
+    torch.cuda.synchronize()
+    pool.reset_all()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pool.run(prep)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print("items %d: one-launch run of %d edges in %.2f ms" % (items, G * 8 * n, dt * 1e3), flush=True)
+    assert pool.sync() == cc.cc.CC_OK
+    for g in range(G):
+        ref = oracle.UnionFind(n)
+        ref.bulk_update(E[g])
+        np.testing.assert_array_equal(outs[g].cpu().numpy(), ref.bulk_query(Qh[g]), err_msg="graph %d" % g)
+    assert dt < 1.0, "one-launch run took %.2f s: the cooperative grid was not resident at once" % dt
     pool.close()
