@@ -273,14 +273,15 @@ __device__ __forceinline__ void filter_refresh_tile(const OpDesc& op, uint32_t t
   const int64_t s0 = w * 32;
   uint32_t fresh = 0;
   if (s0 >= base && s0 + 32 <= end) {
+    // two 16-byte loads in flight at a time: the one-launch form inlines this
+    // beside the update tile, and eight would raise its register count (and
+    // lower its cooperative grid) for a pass that is a small part of a round
     const int4* q = reinterpret_cast<const int4*>(arena + s0);
-    int4 x[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) x[j] = q[j];
     const int32_t l0 = (int32_t)(s0 - base);
-#pragma unroll
+#pragma unroll 2
     for (int j = 0; j < 8; ++j) {
-      const int32_t c[4] = {x[j].x, x[j].y, x[j].z, x[j].w};
+      const int4 x = q[j];
+      const int32_t c[4] = {x.x, x.y, x.z, x.w};
 #pragma unroll
       for (int k = 0; k < 4; ++k)
         if (pid<R>(c[k]) == ra || l0 + 4 * j + k == ra) fresh |= 1u << (4 * j + k);
