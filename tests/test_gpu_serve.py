@@ -29,12 +29,16 @@ def to_gpu(serve, reqs):
     return out
 
 
+@pytest.mark.parametrize("opts", [dict(), dict(hook=2, compress_linked=0, filter=1)],
+                         ids=["default", "rank+filter"])
 @pytest.mark.parametrize("budget_graphs", [None, 3])
-def test_gpu_serving_matches_oracle(serve, budget_graphs):
+def test_gpu_serving_matches_oracle(serve, budget_graphs, opts):
+    # rank+filter: the pool's membership bits across two run streams,
+    # evictions (save, remove) and readmissions (add, load)
     ns, reqs = make_trace(S=12, R=300, rate=5e4, seed=21, nmax=1 << 12)
     want, _ = expected_answers(ns, reqs)
     budget = sum(ns) if budget_graphs is None else max(ns) * budget_graphs
-    ex = serve.GpuExecutor(budget, len(ns) + 1)
+    ex = serve.GpuExecutor(budget, len(ns) + 1, **opts)
     sch = serve.Scheduler(ex, ns, max_inflight=2)
     done = sch.run(to_gpu(serve, reqs))
     torch.cuda.synchronize()
@@ -47,7 +51,7 @@ def test_gpu_serving_matches_oracle(serve, budget_graphs):
     ex.close()
     # one stream alone
     s0 = [r for r in reqs if r.stream == 0]
-    ex = serve.GpuExecutor(ns[0], 2)
+    ex = serve.GpuExecutor(ns[0], 2, **opts)
     done = serve.Scheduler(ex, ns, max_inflight=2).run(to_gpu(serve, s0))
     torch.cuda.synchronize()
     for r in done:
@@ -56,21 +60,23 @@ def test_gpu_serving_matches_oracle(serve, budget_graphs):
     ex.close()
 
 
-def test_gpu_serving_checkpoint_resume(serve):
+@pytest.mark.parametrize("opts", [dict(), dict(hook=2, compress_linked=0, filter=1)],
+                         ids=["default", "rank+filter"])
+def test_gpu_serving_checkpoint_resume(serve, opts):
     """Serve the first half of a trace, checkpoint every stream, drop the
     executor, resume the second half on a fresh one: the answers are those of
     the uninterrupted run (the oracle's)."""
     ns, reqs = make_trace(S=10, R=240, rate=5e4, seed=33, nmax=1 << 12)
     want, _ = expected_answers(ns, reqs)
     first, second = reqs[:120], reqs[120:]
-    ex = serve.GpuExecutor(max(ns) * 4, len(ns) + 1)
+    ex = serve.GpuExecutor(max(ns) * 4, len(ns) + 1, **opts)
     done = serve.Scheduler(ex, ns, max_inflight=2).run(to_gpu(serve, first))
     images = ex.checkpoint()
     ex.close()
     t0 = min(r.arrival for r in second)
     for r in second:
         r.arrival -= t0
-    ex2 = serve.GpuExecutor(max(ns) * 4, len(ns) + 1)
+    ex2 = serve.GpuExecutor(max(ns) * 4, len(ns) + 1, **opts)
     ex2.restore(images)
     done += serve.Scheduler(ex2, ns, max_inflight=2).run(to_gpu(serve, second))
     torch.cuda.synchronize()
