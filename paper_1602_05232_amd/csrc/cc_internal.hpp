@@ -146,23 +146,28 @@ inline bool get_tuning(const Tuning* t, int key, int64_t* v) {
 }
 
 // Upper bound on the blocks of a cooperative launch (every block resident
-// at once): the occupancy calculator's blocks per compute unit, but at most
-// kCoopWavesPerCu wavefronts per unit, times the units.  Two kernels for which
-// the calculator allowed 8 wavefronts per SIMD (its maximum; both with an
-// SGPR allocation of 96) did not become resident at that size on an idle
-// device: the contracting update, 2048 blocks of 256 (1792 resident, 7 per
-// unit), and the pool's one-launch form with 4 items per thread, 1024 blocks
-// of 512 (2.7 s per launch instead of 3 ms: the blocks left out ran only as
-// the spinning ones were preempted).  Grids of at most 7 wavefronts per SIMD
-// have always become resident.  Cooperative grids of this library also
-// never overlap (coop_before/coop_after), and a grid that still cannot
-// become resident ends at the barrier's spin limit with CC_EDEVICE.
-constexpr int kCoopWavesPerCu = 28;  // 7 per SIMD, 4 SIMDs
-
+// at once): the occupancy calculator's blocks per compute unit times the
+// units, less one wavefront per SIMD whenever the calculator allows 7 or
+// more.  The calculator prices SGPRs against a larger register file than
+// the one a grid actually gets: a residency probe (block leaders count in
+// and wait, bounded, for the whole grid) with the same footprint but for
+// its SGPRs found, for blocks of 256 on an idle device, that an SGPR
+// allocation of 96 per wavefront fits 7 wavefronts per SIMD where the
+// calculator says 8, and one of 112 fits 6 where it says 7, while 80 SGPRs
+// (or 61 VGPRs) fit the calculator's 8.  Two kernels of this library hit
+// it: the contracting update, 2048 blocks of 256 (1792 resident), and the
+// pool's one-launch form with 4 items per thread, 1024 blocks of 512 (2.7 s
+// per launch instead of 3 ms: the blocks left out ran only as the spinning
+// ones were preempted).  Bounds below 7 wavefronts per SIMD come from VGPRs
+// or LDS here and are kept.  Cooperative grids of this library also never
+// overlap (coop_before/coop_after), and a grid that still cannot become
+// resident ends at the barrier's spin limit with CC_EDEVICE.
 inline int64_t coop_limit(int per_cu, int cus, int block) {
-  const int waves = (block + 63) / 64;
-  int b = kCoopWavesPerCu / (waves > 0 ? waves : 1);
-  if (per_cu < b) b = per_cu;
+  const int wpb = (block + 63) / 64;             // wavefronts per block
+  const int simd_waves = per_cu * wpb / 4;       // the calculator's wavefronts per SIMD
+  int b = per_cu;
+  if (simd_waves >= 7) b = (simd_waves - 1) * 4 / wpb;
+  if (b > per_cu) b = per_cu;
   return (int64_t)(b > 0 ? b : 1) * cus;
 }
 
