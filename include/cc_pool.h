@@ -60,12 +60,13 @@ int cc_pool_set_stream(cc_pool* p, void* stream);
  * CC_OPT_FILTER 0 or 1 (any other value: CC_EINVAL).  CC_OPT_FILTER 1 is a
  * membership filter per graph (an anchor vertex and one bit per slot of the
  * arena, capacity / 8 bytes, allocated when first turned on; CC_ENOMEM if
- * that fails): before an update round on a graph updated since, one pass
- * over the graph's slots marks the vertices known to be connected to the
- * anchor, and an edge or query pair with both ends marked is settled
- * without a parent read.  The one-launch form reads the marks but does not
- * renew them.  Turning it on clears every mark; reset, reset_all, add and
- * load clear the graph's own.  No option changes a result. */
+ * that fails): before an update round on a graph updated since its marks
+ * were last renewed, one pass over the graph's slots marks the vertices
+ * known to be connected to the anchor, and an edge or query pair with both
+ * ends marked is settled without a parent read.  The one-launch form renews
+ * the marks inside its launch, between two device-wide barriers.  Turning
+ * it on clears every mark; reset, reset_all, add and load clear the graph's
+ * own.  No option changes a result. */
 int cc_pool_set_option(cc_pool* p, int key, int64_t value);
 
 /* Add a graph on vertices [0, n), every vertex alone; *id receives its
