@@ -73,7 +73,7 @@ struct cc_pool {
   uint32_t* member = nullptr;           // membership filter: one bit per arena slot (+1 word)
   int32_t* anchors = nullptr;           // membership filter: anchor vertex per graph handle, -1 for none,
                                         // then (aroot) the anchor's root at the last refresh, -1 for no bits
-  std::vector<uint8_t> stale;           // membership filter: graph updated since its bits were last refreshed
+  std::vector<int64_t> unrefreshed;     // membership filter: update edges since the graph's bits were renewed
   RingSlot ring[kRing];
   int ring_next = 0;
   cc::Tuning tune;
@@ -266,7 +266,7 @@ int filter_clear(cc_pool* p, int64_t base, int64_t n, int32_t g0, int32_t g1) {
   hipLaunchKernelGGL(k_pool_filter_clear, dim3(blocks_for(work, 256, 4096)), dim3(256), 0, p->stream, p->member,
                      base, n, p->anchors, p->anchors + p->max_graphs, g0, g1);
   HIP_TRY(hipGetLastError());
-  for (int32_t g = g0; g < g1; ++g) p->stale[(size_t)g] = 0;
+  for (int32_t g = g0; g < g1; ++g) p->unrefreshed[(size_t)g] = 0;
   return CC_OK;
 }
 
@@ -321,7 +321,7 @@ extern "C" cc_pool* cc_pool_create(int64_t capacity, int32_t max_graphs) {
   p->capacity = capacity;
   p->max_graphs = max_graphs;
   p->graphs.resize((size_t)max_graphs);
-  p->stale.assign((size_t)max_graphs, 0);
+  p->unrefreshed.assign((size_t)max_graphs, 0);
   p->gaps[0] = capacity;
   auto fail = [&](const char* what) -> cc_pool* {
     cc_set_error("cc_pool_create: %s failed", what);
@@ -414,7 +414,8 @@ extern "C" int cc_pool_set_option(cc_pool* p, int key, int64_t value) {
       p->tune.filter = 1;
       // bits kept while the filter was off may describe forests since reset
       if (const int rc = filter_clear(p, 0, p->capacity, 0, p->max_graphs)) return rc;
-      for (int32_t g = 0; g < p->max_graphs; ++g) p->stale[(size_t)g] = p->graphs[(size_t)g].used ? 1 : 0;
+      for (int32_t g = 0; g < p->max_graphs; ++g)  // a forest of unknown age: renew at its next update
+        p->unrefreshed[(size_t)g] = p->graphs[(size_t)g].used ? p->graphs[(size_t)g].n : 0;
       return CC_OK;
     }
     p->tune.filter = (int)value;
@@ -615,8 +616,9 @@ extern "C" int cc_pool_run(cc_pool* p, const cc_op* ops, int32_t num_ops) {
     rtiles[(size_t)r] += (uint32_t)nt;
   }
   // membership filter: refresh descriptors (after the `live` round
-  // descriptors) for the update operations of each round whose graph changed
-  // since its bits were last refreshed; the one-launch form only reads bits
+  // descriptors) for the update operations of each round whose graph has
+  // taken at least n / 8 edges since its bits were last renewed (the
+  // one-launch form renews inside its launch)
   std::vector<int64_t> fstart((size_t)rounds, live), fcount((size_t)rounds, 0);
   std::vector<uint32_t> ftiles((size_t)rounds, 0);
   int64_t nref = 0;
@@ -626,7 +628,11 @@ extern "C" int cc_pool_run(cc_pool* p, const cc_op* ops, int32_t num_ops) {
       fstart[(size_t)r] = live + nref;
       for (int64_t i = rstart[(size_t)r]; i < rstart[(size_t)r + 1]; ++i) {
         const OpDesc& d = slot->host[i];
-        if (d.kind != 0 || !p->stale[(size_t)d.graph]) continue;
+        // renew once the graph has taken n / 8 edges since: the pass costs
+        // O(n), and a stale bit is only a missed shortcut
+        int64_t& since = p->unrefreshed[(size_t)d.graph];
+        if (d.kind != 0 || since == 0 || 8 * since < (int64_t)d.n) continue;
+        since = 0;
         OpDesc& f = slot->host[live + nref++];
         f = d;
         f.tile0 = ftiles[(size_t)r];
@@ -635,7 +641,7 @@ extern "C" int cc_pool_run(cc_pool* p, const cc_op* ops, int32_t num_ops) {
         fcount[(size_t)r]++;
       }
       for (int64_t i = rstart[(size_t)r]; i < rstart[(size_t)r + 1]; ++i)
-        if (slot->host[i].kind == 0) p->stale[(size_t)slot->host[i].graph] = 1;
+        if (slot->host[i].kind == 0) p->unrefreshed[(size_t)slot->host[i].graph] += slot->host[i].count;
     }
   }
   HIP_TRY(hipMemcpyAsync(slot->dev, slot->host, (size_t)(live + nref) * sizeof(OpDesc), hipMemcpyHostToDevice,
@@ -846,7 +852,7 @@ extern "C" int cc_pool_load(cc_pool* p, int32_t id, const void* host_buf) {
   HIP_TRY(hipMemcpyAsync(p->arena + g.base, p->staging, (size_t)g.n * 4, hipMemcpyDeviceToDevice, p->stream));
   HIP_TRY(hipMemcpyAsync(p->glinks + (size_t)id * kPoolLinkStride, &links, 8, hipMemcpyHostToDevice, p->stream));
   if (const int frc = filter_clear(p, g.base, g.n, id, id + 1)) return frc;
-  p->stale[(size_t)id] = 1;
+  p->unrefreshed[(size_t)id] = g.n;  // renew at the next update
   HIP_TRY(hipStreamSynchronize(p->stream));
   return CC_OK;
 }

@@ -57,12 +57,13 @@ __device__ __forceinline__ int block_sum(int v, int* red) {
 // v is known to be connected to a_g.  Components only merge, so a set bit
 // stays true for as long as the graph's forest is not reset, reloaded or
 // moved; the host clears a graph's bits, anchor and anchor root before any
-// of those.  Before an update round on a graph that has changed since its
-// last refresh, k_pool_filter_roots records the anchor's root (choosing the
-// anchor, the first endpoint of the round's first edge, if the graph has
-// none) and k_pool_filter_refresh sets the bits of that root and of every
-// vertex whose parent it is, in one coalesced pass over the graph's slots;
-// under union by rank most of a component hangs directly under its root.
+// of those.  Before an update round on a graph that has taken n / 8 edges or
+// more since its last refresh, k_pool_filter_roots records the anchor's root
+// (choosing the anchor, the first endpoint of the round's first edge, if the
+// graph has none) and k_pool_filter_refresh sets the bits of that root and of
+// every vertex whose parent it is, in one coalesced pass over the graph's
+// slots; under union by rank most of a component hangs directly under its
+// root.
 // Update and query tiles only read bits: an edge or pair whose two bits are
 // set is settled without a parent read.  aroot[g] < 0 means the graph has
 // no bits, and its tiles skip the bitmap.
