@@ -32,6 +32,12 @@
 //            again when the kernel ends.
 // The caller's operation then reads the roots with one load per vertex.
 //
+// With the membership filter (member != null), an item whose two ends are
+// both known to be connected to the filter's anchor is settled without a
+// find: its ends never enter level 0, a query pair of that kind answers 1
+// and an edge of that kind links nothing.  The bits are read, never written,
+// in this kernel; the caller renews them (cc_plain.hip).
+//
 // Storage: level 0 goes to one segment per block (block b takes endpoints
 // [b * seg0_cap, (b + 1) * seg0_cap) and keeps its first visits there).
 // Levels 1, 2, ... are appended in order to one log, so that level l + 1
@@ -291,12 +297,19 @@ __device__ __forceinline__ bool jump(int32_t* parent, int32_t v) {
   return true;
 }
 
+// Both ends of an in-range item known to be connected to the anchor.
+__device__ __forceinline__ bool both_members(const uint32_t* member, int2 p) {
+  return member && bit_test(bit_word(member, p.x), p.x) && bit_test(bit_word(member, p.y), p.y);
+}
+
 // items: int2 array of `count` pairs (edges or query pairs); each pair's two
-// ids form S.  KIND 0 = Bulk-Update, 1 = Bulk-Query (answers to out).
+// ids form S (less the items the membership bits settle).  KIND 0 =
+// Bulk-Update, 1 = Bulk-Query (answers to out).
 template <int KIND, class Ord, int PH2>
 __global__ void k_bulk_find(int32_t* __restrict__ parent, const int2* __restrict__ items, int64_t count,
                             int32_t n, uint8_t* __restrict__ out, BulkFindScratch sc,
-                            unsigned long long* __restrict__ slots, int* __restrict__ flags, unsigned spin_limit) {
+                            unsigned long long* __restrict__ slots, int* __restrict__ flags, unsigned spin_limit,
+                            const uint32_t* __restrict__ member) {
   constexpr bool R = is_ranked<Ord>::value;
   __shared__ int wave_off[17];
   __shared__ int red;
@@ -323,8 +336,11 @@ __global__ void k_bulk_find(int32_t* __restrict__ parent, const int2* __restrict
     int32_t v = -1;
     if (j < j1) {
       const int2 e = items[j >> 1];
-      if (in_range(e, n)) v = (j & 1) ? e.y : e.x;
-      else if ((j & 1) == 0) raise_flag(flags, kFlagRange);
+      if (!in_range(e, n)) {
+        if ((j & 1) == 0) raise_flag(flags, kFlagRange);
+      } else if (!both_members(member, e)) {
+        v = (j & 1) ? e.y : e.x;
+      }
     }
     const bool take = v >= 0 && test_and_set(sc.visited, v);
     int total;
@@ -685,14 +701,15 @@ __global__ void k_bulk_find(int32_t* __restrict__ parent, const int2* __restrict
     for (int64_t i = gtid; i < count; i += gsize) {
       const int2 p = items[i];
       uint8_t ans = 0;
-      if (in_range(p, n)) ans = p.x == p.y || ldp<R>(parent + p.x) == ldp<R>(parent + p.y);
+      // a settled pair's ends were not climbed: its bits answer it
+      if (in_range(p, n)) ans = p.x == p.y || both_members(member, p) || ldp<R>(parent + p.x) == ldp<R>(parent + p.y);
       out[i] = ans;
     }
   } else {
     int links = 0;
     for (int64_t i = gtid; i < count; i += gsize) {
       const int2 p = items[i];
-      if (!in_range(p, n) || p.x == p.y) continue;
+      if (!in_range(p, n) || p.x == p.y || both_members(member, p)) continue;
       const int32_t ru = ldp<R>(parent + p.x), rv = ldp<R>(parent + p.y);  // roots before any link
       if (ru != rv) links += link(parent, ru, rv, n, flags, Ord{}) >= 0;
     }

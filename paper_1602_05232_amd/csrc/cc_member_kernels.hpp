@@ -209,14 +209,16 @@ __global__ void k_member_reseed(const int32_t* __restrict__ parent, int32_t n, c
 #pragma unroll
       for (int k = 0; k < G; ++k) {
         const int64_t w = (i0 + k * stride) >> 5;  // the word of this lane's 32 vertices
-        old[k] = w < words ? bits[w] : 0u;
+        old[k] = w < words ? __hip_atomic_load(bits + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
       }
+      // device-scope stores: this clears bits, and a cleared bit that
+      // another XCD still read as set would be a false proof
 #pragma unroll
       for (int k = 0; k < G; ++k) {
         const int64_t w = (i0 + k * stride) >> 5;
         if (w >= words) continue;
-        if (old[k]) touched[w] |= old[k];
-        bits[w] = fresh[k];
+        if (old[k]) __hip_atomic_fetch_or(touched + w, old[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(bits + w, fresh[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
     }
   }
@@ -231,6 +233,12 @@ __global__ void k_member_ctl_reset(int32_t* __restrict__ ctl, int touched_comple
 // An update that does not maintain the touched bitmap is about to run.
 __global__ void k_member_touched_invalid(int32_t* __restrict__ ctl) {
   if (threadIdx.x == 0) ctl[2] = 0;
+}
+
+// Ask the next k_member_reseed to refill the membership bitmap although the
+// anchor stayed (Bulk-Find sets no bits of its own).
+__global__ void k_member_request_refill(int32_t* __restrict__ ctl) {
+  if (threadIdx.x == 0) __hip_atomic_store(ctl + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ bool touched_complete(const int32_t* ctl) {

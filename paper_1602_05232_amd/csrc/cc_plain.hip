@@ -108,6 +108,7 @@ struct cc_graph {
   uint32_t* member = nullptr;    // membership bitmap of the filter, ceil(n / 32) words
   int32_t* member_ctl = nullptr; // kMemberCtlWords: anchor, refill request, touched-complete flag
   int64_t member_calls = 0;      // fused updates since the filter state was last reset
+  int64_t bf_unrenewed = 0;      // Bulk-Find with the filter: update edges since the bits were last refilled
   bool pristine = true;          // no update or load since creation or the last reset
   bool touched_maybe_complete = false;  // the device's touched-complete flag may be set
   int64_t live_cap = 0;
@@ -267,6 +268,7 @@ void member_reset(cc_graph* g, int touched_complete) {
   hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(2 * words, 256, 4096)), dim3(256), 0, g->stream,
                      (int32_t*)g->member, (int32_t)(2 * words), 0);
   g->member_calls = 0;
+  g->bf_unrenewed = 0;
 }
 
 // An update that does not keep the touched bitmap complete is about to run.
@@ -427,7 +429,7 @@ int read_links(cc_graph* g, unsigned long long* links) {
 }
 
 template <int KIND, class Ord, int PH2>
-int launch_bulk_find_t(cc_graph* g, const int2* items, int64_t count, uint8_t* out) {
+int launch_bulk_find_t(cc_graph* g, const int2* items, int64_t count, uint8_t* out, const uint32_t* member) {
   const int block = 256;
   int per_cu = 0, cus = 0;
   HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bulk_find<KIND, Ord, PH2>, block, 0));
@@ -462,7 +464,7 @@ int launch_bulk_find_t(cc_graph* g, const int2* items, int64_t count, uint8_t* o
   unsigned long long* slots = g->slots;
   int* flags = g->flags;
   unsigned spin = (unsigned)g->tune.spin_limit;
-  void* args[] = {&parent, &items, &count, &n, &out, &sc, &slots, &flags, &spin};
+  void* args[] = {&parent, &items, &count, &n, &out, &sc, &slots, &flags, &spin, &member};
   if (const int crc = cc::coop_before(g->stream)) return crc;
   HIP_TRY(hipLaunchCooperativeKernel((const void*)k_bulk_find<KIND, Ord, PH2>, dim3((unsigned)grid), dim3(block),
                                      args, 0, g->stream));
@@ -519,6 +521,30 @@ int launch_contract_t(cc_graph* g, const int2* e, int64_t m) {
   return CC_OK;
 }
 
+// Bulk-Find sets no membership bits, so before an update it refills them
+// from `parent` (the anchor root and its direct children, which after a
+// Bulk-Find are most of its trail) once n / 8 edges have gone in since the
+// last refill, besides the anchor picks of the fused path's schedule.
+template <bool R>
+void bf_member_renew(cc_graph* g, const int2* e, int64_t m) {
+  const int64_t c = g->member_calls++;
+  const bool pick = (c & (c - 1)) == 0 || c % 64 == 0;
+  const bool renew = 8 * g->bf_unrenewed >= g->n;
+  if (pick)
+    hipLaunchKernelGGL(k_anchor_pick<R>, dim3(1), dim3(kPickThreads), 0, g->stream, g->parent, e, m,
+                       (int32_t)g->n, g->member_ctl, g->flags);
+  if (renew) {
+    hipLaunchKernelGGL(k_member_request_refill, dim3(1), dim3(64), 0, g->stream, g->member_ctl);
+    g->bf_unrenewed = 0;
+  }
+  if (pick || renew)
+    hipLaunchKernelGGL(k_member_reseed<R>, dim3(blocks_for(g->n, 256, 1024)), dim3(256), 0, g->stream, g->parent,
+                       (int32_t)g->n, g->member_ctl, g->member, member_words(g), g->flags);
+  g->bf_unrenewed += m;
+}
+
+// member: the membership bits Bulk-Find may settle items with (updates with
+// the filter on; queries with filter 2), or null.
 template <int KIND>
 int launch_bulk_find(cc_graph* g, const int2* items, int64_t count, uint8_t* out) {
   if (g->capturing) {
@@ -527,14 +553,21 @@ int launch_bulk_find(cc_graph* g, const int2* items, int64_t count, uint8_t* out
   }
   int rc = alloc_bulkfind(g);
   if (rc != CC_OK) return rc;
-  if (g->tune.find == 2) {
-    if (g->tune.hook == 1) return launch_bulk_find_t<KIND, ByHash, 1>(g, items, count, out);
-    if (g->tune.hook == 2) return launch_bulk_find_t<KIND, ByRank, 1>(g, items, count, out);
-    return launch_bulk_find_t<KIND, ById, 1>(g, items, count, out);
+  const bool use = g->member && (KIND == 0 ? g->tune.filter != 0 : g->tune.filter == 2);
+  const uint32_t* member = use ? g->member : nullptr;
+  if (use && KIND == 0) {
+    if (g->tune.hook == 2) bf_member_renew<true>(g, items, count);
+    else bf_member_renew<false>(g, items, count);
+    HIP_TRY(hipGetLastError());
   }
-  if (g->tune.hook == 1) return launch_bulk_find_t<KIND, ByHash, 0>(g, items, count, out);
-  if (g->tune.hook == 2) return launch_bulk_find_t<KIND, ByRank, 0>(g, items, count, out);
-  return launch_bulk_find_t<KIND, ById, 0>(g, items, count, out);
+  if (g->tune.find == 2) {
+    if (g->tune.hook == 1) return launch_bulk_find_t<KIND, ByHash, 1>(g, items, count, out, member);
+    if (g->tune.hook == 2) return launch_bulk_find_t<KIND, ByRank, 1>(g, items, count, out, member);
+    return launch_bulk_find_t<KIND, ById, 1>(g, items, count, out, member);
+  }
+  if (g->tune.hook == 1) return launch_bulk_find_t<KIND, ByHash, 0>(g, items, count, out, member);
+  if (g->tune.hook == 2) return launch_bulk_find_t<KIND, ByRank, 0>(g, items, count, out, member);
+  return launch_bulk_find_t<KIND, ById, 0>(g, items, count, out, member);
 }
 
 // Compaction threshold: fold finished link-counter snapshots into the
@@ -804,6 +837,10 @@ extern "C" int cc_bulk_update(cc_graph* g, const int32_t* edges, int64_t m) {
   DeviceGuard dg(g->device);
   const int2* e = reinterpret_cast<const int2*>(edges);
   if (g->tune.find != 0) {
+    if (g->tune.filter && !g->member) {
+      const int arc = alloc_member(g);  // before the touched bitmap is marked incomplete
+      if (arc != CC_OK) return arc;
+    }
     member_touched_invalid(g);
     int rc = launch_bulk_find<0>(g, e, m, nullptr);
     if (rc == CC_OK) {

@@ -46,6 +46,10 @@ OPTION_SETS = [
     dict(update_mode=0, split_below=100, hook=2),
     dict(update_mode=0, split_below=60, hook=0, compress_linked=0),
     dict(update_mode=0, split_below=100, hook=1, filter=2),
+    dict(find=1, hook=2, filter=2),
+    dict(find=1, hook=1, filter=1, grid_cap=5),
+    dict(find=2, hook=2, filter=2, grid_cap=16),
+    dict(find=2, hook=0, filter=2),
 ]
 
 
