@@ -35,8 +35,14 @@
 // With the membership filter (member != null), an item whose two ends are
 // both known to be connected to the filter's anchor is settled without a
 // find: its ends never enter level 0, a query pair of that kind answers 1
-// and an edge of that kind links nothing.  The bits are read, never written,
-// in this kernel; the caller renews them (cc_plain.hip).
+// and an edge of that kind links nothing.  The membership bits are read,
+// never written, in this kernel; the caller renews them (cc_plain.hip).
+// The touched bitmap (member + words, every vertex that has had an edge) is
+// kept by Bulk-Update: both ends of every edge it does not settle are
+// marked (a settled edge's ends are members, which have had edges).  While
+// the device flag says it is complete (ctl[2]), a Bulk-Query pair with an
+// end that never had an edge is settled as well: it answers whether its two
+// ids are equal.
 //
 // Storage: level 0 goes to one segment per block (block b takes endpoints
 // [b * seg0_cap, (b + 1) * seg0_cap) and keeps its first visits there).
@@ -302,6 +308,16 @@ __device__ __forceinline__ bool both_members(const uint32_t* member, int2 p) {
   return member && bit_test(bit_word(member, p.x), p.x) && bit_test(bit_word(member, p.y), p.y);
 }
 
+// A query pair with an end that never had an edge (touched complete).
+__device__ __forceinline__ bool lone_end(const uint32_t* touched, int2 p) {
+  return touched && !(bit_test(bit_word(touched, p.x), p.x) && bit_test(bit_word(touched, p.y), p.y));
+}
+
+// Mark v as having had an edge (read first: most are marked already).
+__device__ __forceinline__ void mark_touched(uint32_t* touched, int32_t v) {
+  if (!bit_test(bit_word_l2(touched, v), v)) bit_set(touched, v);
+}
+
 // items: int2 array of `count` pairs (edges or query pairs); each pair's two
 // ids form S (less the items the membership bits settle).  KIND 0 =
 // Bulk-Update, 1 = Bulk-Query (answers to out).
@@ -309,7 +325,8 @@ template <int KIND, class Ord, int PH2>
 __global__ void k_bulk_find(int32_t* __restrict__ parent, const int2* __restrict__ items, int64_t count,
                             int32_t n, uint8_t* __restrict__ out, BulkFindScratch sc,
                             unsigned long long* __restrict__ slots, int* __restrict__ flags, unsigned spin_limit,
-                            const uint32_t* __restrict__ member) {
+                            const uint32_t* __restrict__ member, uint32_t* __restrict__ touched_bits,
+                            const int32_t* __restrict__ member_ctl) {
   constexpr bool R = is_ranked<Ord>::value;
   __shared__ int wave_off[17];
   __shared__ int red;
@@ -325,6 +342,8 @@ __global__ void k_bulk_find(int32_t* __restrict__ parent, const int2* __restrict
   unsigned* bar = sc.ctl + kBfBar;
   const int slot = (int)(blockIdx.x % kCountSlots) * kCountStride;
   unsigned gen = 0;
+  // queries: the touched bitmap, while the device says it is complete
+  const uint32_t* touched = KIND == 1 && touched_bits && touched_complete(member_ctl) ? touched_bits : nullptr;
 
   // level 0: this block's share of the 2 * count endpoints
   const int64_t j0 = (int64_t)blockIdx.x * sc.seg0_cap;
@@ -338,7 +357,7 @@ __global__ void k_bulk_find(int32_t* __restrict__ parent, const int2* __restrict
       const int2 e = items[j >> 1];
       if (!in_range(e, n)) {
         if ((j & 1) == 0) raise_flag(flags, kFlagRange);
-      } else if (!both_members(member, e)) {
+      } else if (!both_members(member, e) && !(KIND == 1 && e.x != e.y && lone_end(touched, e))) {
         v = (j & 1) ? e.y : e.x;
       }
     }
@@ -702,7 +721,9 @@ __global__ void k_bulk_find(int32_t* __restrict__ parent, const int2* __restrict
       const int2 p = items[i];
       uint8_t ans = 0;
       // a settled pair's ends were not climbed: its bits answer it
-      if (in_range(p, n)) ans = p.x == p.y || both_members(member, p) || ldp<R>(parent + p.x) == ldp<R>(parent + p.y);
+      if (in_range(p, n))
+        ans = p.x == p.y || (!lone_end(touched, p) &&
+                             (both_members(member, p) || ldp<R>(parent + p.x) == ldp<R>(parent + p.y)));
       out[i] = ans;
     }
   } else {
@@ -710,6 +731,10 @@ __global__ void k_bulk_find(int32_t* __restrict__ parent, const int2* __restrict
     for (int64_t i = gtid; i < count; i += gsize) {
       const int2 p = items[i];
       if (!in_range(p, n) || p.x == p.y || both_members(member, p)) continue;
+      if (touched_bits) {
+        mark_touched(touched_bits, p.x);
+        mark_touched(touched_bits, p.y);
+      }
       const int32_t ru = ldp<R>(parent + p.x), rv = ldp<R>(parent + p.y);  // roots before any link
       if (ru != rv) links += link(parent, ru, rv, n, flags, Ord{}) >= 0;
     }

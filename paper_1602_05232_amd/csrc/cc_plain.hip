@@ -429,7 +429,8 @@ int read_links(cc_graph* g, unsigned long long* links) {
 }
 
 template <int KIND, class Ord, int PH2>
-int launch_bulk_find_t(cc_graph* g, const int2* items, int64_t count, uint8_t* out, const uint32_t* member) {
+int launch_bulk_find_t(cc_graph* g, const int2* items, int64_t count, uint8_t* out, const uint32_t* member,
+                       uint32_t* touched, const int32_t* member_ctl) {
   const int block = 256;
   int per_cu = 0, cus = 0;
   HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bulk_find<KIND, Ord, PH2>, block, 0));
@@ -464,7 +465,7 @@ int launch_bulk_find_t(cc_graph* g, const int2* items, int64_t count, uint8_t* o
   unsigned long long* slots = g->slots;
   int* flags = g->flags;
   unsigned spin = (unsigned)g->tune.spin_limit;
-  void* args[] = {&parent, &items, &count, &n, &out, &sc, &slots, &flags, &spin, &member};
+  void* args[] = {&parent, &items, &count, &n, &out, &sc, &slots, &flags, &spin, &member, &touched, &member_ctl};
   if (const int crc = cc::coop_before(g->stream)) return crc;
   HIP_TRY(hipLaunchCooperativeKernel((const void*)k_bulk_find<KIND, Ord, PH2>, dim3((unsigned)grid), dim3(block),
                                      args, 0, g->stream));
@@ -543,8 +544,10 @@ void bf_member_renew(cc_graph* g, const int2* e, int64_t m) {
   g->bf_unrenewed += m;
 }
 
-// member: the membership bits Bulk-Find may settle items with (updates with
-// the filter on; queries with filter 2), or null.
+// member: the membership bits Bulk-Find may settle items with, and the
+// touched bitmap after them (updates with the filter on keep it; queries
+// with filter 2 read it while the device flag says it is complete), or
+// null.
 template <int KIND>
 int launch_bulk_find(cc_graph* g, const int2* items, int64_t count, uint8_t* out) {
   if (g->capturing) {
@@ -555,19 +558,21 @@ int launch_bulk_find(cc_graph* g, const int2* items, int64_t count, uint8_t* out
   if (rc != CC_OK) return rc;
   const bool use = g->member && (KIND == 0 ? g->tune.filter != 0 : g->tune.filter == 2);
   const uint32_t* member = use ? g->member : nullptr;
+  uint32_t* touched = use ? g->member + member_words(g) : nullptr;
+  const int32_t* ctl = use ? g->member_ctl : nullptr;
   if (use && KIND == 0) {
     if (g->tune.hook == 2) bf_member_renew<true>(g, items, count);
     else bf_member_renew<false>(g, items, count);
     HIP_TRY(hipGetLastError());
   }
   if (g->tune.find == 2) {
-    if (g->tune.hook == 1) return launch_bulk_find_t<KIND, ByHash, 1>(g, items, count, out, member);
-    if (g->tune.hook == 2) return launch_bulk_find_t<KIND, ByRank, 1>(g, items, count, out, member);
-    return launch_bulk_find_t<KIND, ById, 1>(g, items, count, out, member);
+    if (g->tune.hook == 1) return launch_bulk_find_t<KIND, ByHash, 1>(g, items, count, out, member, touched, ctl);
+    if (g->tune.hook == 2) return launch_bulk_find_t<KIND, ByRank, 1>(g, items, count, out, member, touched, ctl);
+    return launch_bulk_find_t<KIND, ById, 1>(g, items, count, out, member, touched, ctl);
   }
-  if (g->tune.hook == 1) return launch_bulk_find_t<KIND, ByHash, 0>(g, items, count, out, member);
-  if (g->tune.hook == 2) return launch_bulk_find_t<KIND, ByRank, 0>(g, items, count, out, member);
-  return launch_bulk_find_t<KIND, ById, 0>(g, items, count, out, member);
+  if (g->tune.hook == 1) return launch_bulk_find_t<KIND, ByHash, 0>(g, items, count, out, member, touched, ctl);
+  if (g->tune.hook == 2) return launch_bulk_find_t<KIND, ByRank, 0>(g, items, count, out, member, touched, ctl);
+  return launch_bulk_find_t<KIND, ById, 0>(g, items, count, out, member, touched, ctl);
 }
 
 // Compaction threshold: fold finished link-counter snapshots into the
@@ -838,10 +843,10 @@ extern "C" int cc_bulk_update(cc_graph* g, const int32_t* edges, int64_t m) {
   const int2* e = reinterpret_cast<const int2*>(edges);
   if (g->tune.find != 0) {
     if (g->tune.filter && !g->member) {
-      const int arc = alloc_member(g);  // before the touched bitmap is marked incomplete
+      const int arc = alloc_member(g);
       if (arc != CC_OK) return arc;
     }
-    member_touched_invalid(g);
+    if (!g->tune.filter) member_touched_invalid(g);  // with the filter, Bulk-Find keeps it
     int rc = launch_bulk_find<0>(g, e, m, nullptr);
     if (rc == CC_OK) {
       g->updates++;

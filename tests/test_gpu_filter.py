@@ -88,6 +88,24 @@ def test_rmat_bits_are_proofs_and_the_anchor_is_the_giant(cc, opts):
     g.close()
 
 
+@pytest.mark.parametrize("opts", [dict(find=1, hook=2, filter=2), dict(find=2, hook=1, filter=2),
+                                  dict(find=1, hook=0, filter=1, grid_cap=7)],
+                         ids=lambda o: ",".join("%s=%s" % kv for kv in sorted(o.items())))
+def test_bulk_find_with_the_filter_keeps_both_bitmaps(cc, opts):
+    """Bulk-Find under the filter: the membership bits it settles items with
+    stay proofs, its updates keep the touched bitmap complete (queries then
+    settle pairs with an end that never had an edge), and every answer and
+    label is the oracle's."""
+    s = synth.rmat_stream(scale=15, size_lo=8, size_hi=15, qbatch=1 << 11)
+    g, ref = run(cc, s, opts)
+    anchor, got = check_bits(g, ref, "at the end")
+    assert g.filter_state()[1], "touched bitmap no longer complete"
+    lab = ref.labels()
+    sizes = np.bincount(lab, minlength=s.n)
+    assert anchor >= 0 and len(got) > sizes.max() // 2, "the refills did not engage"
+    g.close()
+
+
 def test_anchor_moves_to_the_larger_component_and_the_bitmap_is_refilled(cc):
     n = 1 << 15
     rng = np.random.default_rng(5)
