@@ -13,7 +13,11 @@
 // back or invalidates the whole L2 of the XCD, and thousands of them per
 // barrier dominated its cost.  The arrival counter, the generation and the
 // abort word sit on separate 128-byte lines, so waiting blocks polling the
-// generation do not contend with arrivals.  Waiting is bounded: past the
+// generation do not contend with arrivals.  Arrivals on one address are
+// served one at a time (about 12 ns each), so a grid of kBarSubMin blocks or
+// more counts in on kBarSub sub-counters (block b on b mod kBarSub), and only
+// the last arrival of each sub-group counts in on the top counter; it first
+// passes its sub-group's releases on with an acquire-release fence.  Waiting is bounded: past the
 // spin limit a block raises the timeout flag and the abort word, and every
 // block leaves the kernel at its next barrier.
 //
@@ -30,8 +34,11 @@ namespace ccdev {
 namespace {
 
 // Barrier state: bar[0] arrivals (monotone within a launch), bar[32]
-// generation, bar[64] abort; all zero at launch.
-constexpr int kBarWords = 96;
+// generation, bar[64] abort, bar[96 + 32 s] arrivals of sub-group s; all zero
+// at launch.
+constexpr int kBarSub = 16;
+constexpr int kBarSubMin = 128;
+constexpr int kBarWords = 96 + 32 * kBarSub;
 
 __device__ __forceinline__ unsigned bar_load(unsigned* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -49,11 +56,29 @@ __device__ __forceinline__ bool grid_sync(unsigned* bar, unsigned& gen, int* fla
     if (FENCE) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     const unsigned target = gen + 1;
     int good = 1;
-    const unsigned arrived = __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
-    if (arrived == gridDim.x * target) {
+    bool last;
+    if (gridDim.x < (unsigned)kBarSubMin) {
+      const unsigned arrived = __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+      last = arrived == gridDim.x * target;
+    } else {
+      const unsigned s = blockIdx.x % kBarSub;
+      const unsigned members = (gridDim.x - s + kBarSub - 1) / kBarSub;
+      const unsigned a = __hip_atomic_fetch_add(bar + 96 + 32 * s, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+      last = false;
+      if (a == members * target) {
+        // the sub-group's last arrival: its acquire half synchronizes with
+        // the members' release fences, its release half with the top-level
+        // last arrival's acquire fence below
+        if (FENCE) __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+        const unsigned t = __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+        last = t == (unsigned)kBarSub * target;
+      }
+    }
+    if (last) {
       // The last arrival passes the others' releases on: its acquire fence
-      // synchronizes with every block's release fence (their increments are
-      // in the release sequence it read), and its release store of the
+      // synchronizes with every block's release fence (a large grid's:
+      // every sub-group leader's acquire-release fence), their increments
+      // being in the release sequence it read, and its release store of the
       // generation with every waiter's acquire fence below.
       if (FENCE) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       __hip_atomic_store(bar + 32, target, FENCE ? __ATOMIC_RELEASE : __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
