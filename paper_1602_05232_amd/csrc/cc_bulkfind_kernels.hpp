@@ -44,8 +44,9 @@
 // end that never had an edge is settled as well: it answers whether its two
 // ids are equal.
 //
-// Storage: level 0 goes to one segment per block (block b takes endpoints
-// [b * seg0_cap, (b + 1) * seg0_cap) and keeps its first visits there).
+// Storage: level 0 goes to one segment per block (block b takes items
+// [b * seg0_cap / 2, (b + 1) * seg0_cap / 2) and keeps the first visits of
+// their ends in [b * seg0_cap, (b + 1) * seg0_cap)).
 // Levels 1, 2, ... are appended in order to one log, so that level l + 1
 // occupies the log range reserved while level l was read.  Each level
 // reserves through a counter of its own (a ring of three, cleared two
@@ -345,26 +346,41 @@ __global__ void k_bulk_find(int32_t* __restrict__ parent, const int2* __restrict
   // queries: the touched bitmap, while the device says it is complete
   const uint32_t* touched = KIND == 1 && touched_bits && touched_complete(member_ctl) ? touched_bits : nullptr;
 
-  // level 0: this block's share of the 2 * count endpoints
-  const int64_t j0 = (int64_t)blockIdx.x * sc.seg0_cap;
-  const int64_t j1 = j0 + sc.seg0_cap < 2 * count ? j0 + sc.seg0_cap : 2 * count;
-  int32_t* seg = sc.seg0 + j0;
+  // level 0: this block's share of the items (seg0_cap / 2 of them, room
+  // for both ends of each).  A query pair settled here gets its answer now,
+  // an open one the mark kOpen, answered after Phase II.
+  constexpr uint8_t kOpen = 2;
+  const int64_t per = sc.seg0_cap >> 1;
+  const int64_t i0 = (int64_t)blockIdx.x * per;
+  const int64_t i1 = i0 + per < count ? i0 + per : count;
+  int32_t* seg = sc.seg0 + 2 * i0;
   int64_t cnt0 = 0;
-  for (int64_t t0 = j0; t0 < j1; t0 += B) {
-    const int64_t j = t0 + tid;
-    int32_t v = -1;
-    if (j < j1) {
-      const int2 e = items[j >> 1];
+  for (int64_t t0 = i0; t0 < i1; t0 += B) {
+    const int64_t i = t0 + tid;
+    int32_t a = -1, b = -1;
+    if (i < i1) {
+      const int2 e = items[i];
       if (!in_range(e, n)) {
-        if ((j & 1) == 0) raise_flag(flags, kFlagRange);
-      } else if (!both_members(member, e) && !(KIND == 1 && e.x != e.y && lone_end(touched, e))) {
-        v = (j & 1) ? e.y : e.x;
+        raise_flag(flags, kFlagRange);
+        if (KIND == 1) out[i] = 0;
+      } else if (e.x == e.y) {
+        if (KIND == 1) out[i] = 1;  // an edge from a vertex to itself changes nothing
+      } else if (KIND == 1 && lone_end(touched, e)) {
+        out[i] = 0;
+      } else if (both_members(member, e)) {
+        if (KIND == 1) out[i] = 1;
+      } else {
+        if (KIND == 1) out[i] = kOpen;
+        a = e.x;
+        b = e.y;
       }
     }
-    const bool take = v >= 0 && test_and_set(sc.visited, v);
+    const bool ta = a >= 0 && test_and_set(sc.visited, a);
+    const bool tb = b >= 0 && test_and_set(sc.visited, b);
     int total;
-    const int off = block_scan(take ? 1 : 0, &total, wave_off);
-    if (take) seg[cnt0 + off] = v;
+    const int off = block_scan((int)ta + (int)tb, &total, wave_off);
+    if (ta) seg[cnt0 + off] = a;
+    if (tb) seg[cnt0 + off + (ta ? 1 : 0)] = b;
     cnt0 += total;
   }
   if (tid == 0 && cnt0 > 0) atomicAdd(count_group(groups, 0) + slot, (unsigned)cnt0);
@@ -717,14 +733,11 @@ __global__ void k_bulk_find(int32_t* __restrict__ parent, const int2* __restrict
 
   // the operation itself
   if (KIND == 1) {
+    // the open pairs: both ends were climbed and point at their roots
     for (int64_t i = gtid; i < count; i += gsize) {
+      if (out[i] != kOpen) continue;
       const int2 p = items[i];
-      uint8_t ans = 0;
-      // a settled pair's ends were not climbed: its bits answer it
-      if (in_range(p, n))
-        ans = p.x == p.y || (!lone_end(touched, p) &&
-                             (both_members(member, p) || ldp<R>(parent + p.x) == ldp<R>(parent + p.y)));
-      out[i] = ans;
+      out[i] = ldp<R>(parent + p.x) == ldp<R>(parent + p.y);
     }
   } else {
     int links = 0;

@@ -438,8 +438,8 @@ int launch_bulk_find_t(cc_graph* g, const int2* items, int64_t count, uint8_t* o
   int64_t grid = (2 * count + block - 1) / block;
   grid = std::min<int64_t>(std::min<int64_t>(grid, cc::coop_limit(per_cu, cus, block)), 1024);
   grid = std::max<int64_t>(1, std::min<int64_t>(grid, (int64_t)g->tune.grid_cap));
-  // level 0 takes one segment per block of the 2 * count endpoints
-  const int64_t seg0_cap = (2 * count + grid - 1) / grid;
+  // level 0 takes one segment per block: room for both ends of its items
+  const int64_t seg0_cap = 2 * ((count + grid - 1) / grid);
   if (seg0_cap * grid > g->bf_seg0_entries) {
     HIP_TRY(hipStreamSynchronize(g->stream));
     (void)hipFree(g->bf.seg0);
