@@ -122,16 +122,19 @@ enum cc_option {
    * members is dropped without a find (it could only join a component with
    * itself); 2 = that, and Bulk-Query answers without a find a pair of two
    * members (1) and, while every update since the last reset went through
-   * the filtered fused schedule, a pair with an end outside the touched
-   * bitmap (0: that vertex never had an edge); its finds also add the
-   * endpoints they prove connected.  cc_labels uses the bitmaps whenever
-   * they exist.  Bits are set only from proofs, so results are unchanged.
-   * Choosing the anchor costs one single-block launch and one launch that
-   * refills the membership bitmap when the anchor changes (a pass over the
-   * parent array), before update calls 0, 1, 2, 4, 8, ... and every 64th
-   * call after a reset or load.  The split and contracting schedules,
-   * Bulk-Find and cc_bulk_stream neither use nor update the bitmaps.
-   * Default 0. */
+   * the filtered fused schedule or filtered Bulk-Find, a pair with an end
+   * outside the touched bitmap (0: that vertex never had an edge); its finds
+   * also add the endpoints they prove connected.  cc_labels uses the bitmaps
+   * whenever they exist.  Bits are set only from proofs, so results are
+   * unchanged.  Choosing the anchor costs one single-block launch and one
+   * launch that refills the membership bitmap when the anchor changes (a
+   * pass over the parent array), before update calls 0, 1, 2, 4, 8, ... and
+   * every 64th call after a reset or load.  With CC_OPT_FIND 1 or 2,
+   * Bulk-Find settles the same items before its climb and keeps the touched
+   * bitmap; it sets no membership bits itself, so the bitmap is also
+   * refilled before a Bulk-Update once n / 8 edges have gone in since the
+   * last refill.  The split and contracting schedules and cc_bulk_stream
+   * neither use nor update the bitmaps.  Default 0. */
   CC_OPT_FILTER = 12,
   /* Pairs per thread of Bulk-Query: 1, 2, 4 or 8, or 0 = as CC_OPT_ITEMS
    * (default), for when queries and updates want different amounts of work
@@ -252,8 +255,9 @@ int cc_count_roots(cc_graph* g, int64_t* out);
 /* State of the membership filter (CC_OPT_FILTER), for checks.  *anchor gets
  * the anchor vertex (-1 if none, or if the filter has not run since the
  * last reset or load).  *touched_complete gets 1 while every update since
- * the last reset went through the filtered fused form, so that the touched
- * bitmap is complete, else 0.  Unless bits is NULL, it gets 2 * ceil(n / 32)
+ * the last reset went through the filtered fused form or filtered
+ * Bulk-Find, so that the touched bitmap is complete, else 0.  Unless bits
+ * is NULL, it gets 2 * ceil(n / 32)
  * HOST uint32 words: the membership bitmap, then the touched bitmap, vertex
  * v at bit v % 32 of word v / 32 of each (all zero if the filter has never
  * run).  Every vertex in the membership bitmap is connected to the anchor;
