@@ -257,10 +257,9 @@ int cc_count_roots(cc_graph* g, int64_t* out);
  * last reset or load).  *touched_complete gets 1 while every update since
  * the last reset went through the filtered fused form or filtered
  * Bulk-Find, so that the touched bitmap is complete, else 0.  Unless bits
- * is NULL, it gets 2 * ceil(n / 32)
- * HOST uint32 words: the membership bitmap, then the touched bitmap, vertex
- * v at bit v % 32 of word v / 32 of each (all zero if the filter has never
- * run).  Every vertex in the membership bitmap is connected to the anchor;
+ * is NULL, it gets 2 * ceil(n / 32) HOST uint32 words: the membership
+ * bitmap, then the touched bitmap, vertex v at bit v % 32 of word v / 32 of
+ * each (all zero if the filter has never run).  Every vertex in the membership bitmap is connected to the anchor;
  * while touched_complete is 1, every vertex in neither bitmap is alone in
  * its component.  Waits for the stream. */
 int cc_filter_state(cc_graph* g, int32_t* anchor, int32_t* touched_complete, uint32_t* bits);
