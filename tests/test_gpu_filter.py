@@ -168,8 +168,9 @@ def test_reset_load_and_tiny_ragged_sizes(cc):
 
 
 def test_filter_with_other_schedules_keeps_bits_sound(cc):
-    """Switching schedule mid-stream: the split and contracting schedules and
-    Bulk-Find leave the bitmap alone, and what it holds stays true."""
+    """Switching schedule mid-stream: the split and contracting schedules
+    leave the bitmaps alone, Bulk-Find refills the membership bits and keeps
+    the touched ones, and what the bitmaps hold stays true."""
     s = synth.rmat_stream(scale=14, size_lo=8, size_hi=13, qbatch=1 << 10)
     g = cc.Graph(s.n, filter=2)
     ref = oracle.UnionFind(s.n)
