@@ -106,6 +106,9 @@ def test_random_pool_config(cc, seed):
     run (so runs have several rounds), against one oracle per graph."""
     rng = np.random.default_rng(5000 + seed)
     opts = pool_options(rng)
+    # the pool's membership filter, from a generator of its own so that the
+    # other draws of a seed stay as they were before the option existed
+    opts["filter"] = int(np.random.default_rng(seed + 15485863).integers(2))
     G = int(rng.integers(1, 40))
     ns = [int(x) for x in rng.integers(1, 3000, size=G)]
     print("pool case %d: G=%d sum_n=%d opts=%s" % (seed, G, sum(ns), opts), flush=True)
