@@ -135,6 +135,7 @@ constexpr int64_t kRdGrid = 1 << 15;
 struct BulkFindScratch {
   uint32_t* visited;  // n bits, all clear at rest
   int32_t* seg0;      // level 0, seg0_cap entries per block
+  uint32_t* open;     // Bulk-Update: seg0_cap / 2 entries per block, the items level 0 left open (or null)
   int32_t* log;       // levels 1, 2, ..., -1 in chunk padding
   unsigned* ctl;      // kBulkFindCtlWords, zero at launch
   int64_t seg0_cap;   // level-0 entries per block
@@ -355,6 +356,9 @@ __global__ void k_bulk_find(int32_t* __restrict__ parent, const int2* __restrict
   const int64_t i1 = i0 + per < count ? i0 + per : count;
   int32_t* seg = sc.seg0 + 2 * i0;
   int64_t cnt0 = 0;
+  // Bulk-Update: the block's open items, listed for the linking at the end
+  uint32_t* open = KIND == 0 ? sc.open : nullptr;
+  int64_t nopen = 0;
   for (int64_t t0 = i0; t0 < i1; t0 += B) {
     const int64_t i = t0 + tid;
     int32_t a = -1, b = -1;
@@ -377,11 +381,16 @@ __global__ void k_bulk_find(int32_t* __restrict__ parent, const int2* __restrict
     }
     const bool ta = a >= 0 && test_and_set(sc.visited, a);
     const bool tb = b >= 0 && test_and_set(sc.visited, b);
+    // one scan for both counts: kept ends in the low 16 bits (at most 2 per
+    // thread and 2048 per pass), open items above
+    const bool op = open && a >= 0;
     int total;
-    const int off = block_scan((int)ta + (int)tb, &total, wave_off);
-    if (ta) seg[cnt0 + off] = a;
-    if (tb) seg[cnt0 + off + (ta ? 1 : 0)] = b;
-    cnt0 += total;
+    const int off = block_scan((int)ta + (int)tb + ((int)op << 16), &total, wave_off);
+    if (ta) seg[cnt0 + (off & 0xffff)] = a;
+    if (tb) seg[cnt0 + (off & 0xffff) + (ta ? 1 : 0)] = b;
+    if (op) open[i0 + nopen + (off >> 16)] = (uint32_t)i;
+    cnt0 += total & 0xffff;
+    nopen += total >> 16;
   }
   if (tid == 0 && cnt0 > 0) atomicAdd(count_group(groups, 0) + slot, (unsigned)cnt0);
   bool alive = grid_sync(bar, gen, flags, spin_limit);
@@ -741,9 +750,13 @@ __global__ void k_bulk_find(int32_t* __restrict__ parent, const int2* __restrict
     }
   } else {
     int links = 0;
-    for (int64_t i = gtid; i < count; i += gsize) {
+    // every item, or only the open ones this block listed at level 0 (the
+    // others are out of range, self-loops or settled by the bits)
+    const int64_t lim = open ? nopen : count, first = open ? tid : gtid, step = open ? B : gsize;
+    for (int64_t k = first; k < lim; k += step) {
+      const int64_t i = open ? (int64_t)open[i0 + k] : k;
       const int2 p = items[i];
-      if (!in_range(p, n) || p.x == p.y || both_members(member, p)) continue;
+      if (!open && (!in_range(p, n) || p.x == p.y || both_members(member, p))) continue;
       if (touched_bits) {
         mark_touched(touched_bits, p.x);
         mark_touched(touched_bits, p.y);

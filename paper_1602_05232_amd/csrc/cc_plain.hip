@@ -224,6 +224,7 @@ void free_bulkfind(cc_graph* g) {
   (void)hipFree(b.seg0);
   (void)hipFree(b.log);
   (void)hipFree(b.ctl);
+  (void)hipFree(b.open);
   b = BulkFindScratch{};
   g->bf_ready = false;
   g->bf_seg0_entries = 0;
@@ -443,10 +444,16 @@ int launch_bulk_find_t(cc_graph* g, const int2* items, int64_t count, uint8_t* o
   if (seg0_cap * grid > g->bf_seg0_entries) {
     HIP_TRY(hipStreamSynchronize(g->stream));
     (void)hipFree(g->bf.seg0);
+    (void)hipFree(g->bf.open);
     g->bf.seg0 = nullptr;
+    g->bf.open = nullptr;
     g->bf_seg0_entries = 0;
-    if (hipMalloc(&g->bf.seg0, (size_t)(seg0_cap * grid) * 4) != hipSuccess) {
+    // the open-item lists take half as many entries as level 0
+    if (hipMalloc(&g->bf.seg0, (size_t)(seg0_cap * grid) * 4) != hipSuccess ||
+        hipMalloc(&g->bf.open, (size_t)(seg0_cap * grid / 2) * 4) != hipSuccess) {
+      (void)hipFree(g->bf.seg0);
       g->bf.seg0 = nullptr;
+      g->bf.open = nullptr;
       cc_set_error("Bulk-Find: hipMalloc of %lld level-0 entries failed", (long long)(seg0_cap * grid));
       return CC_ENOMEM;
     }
@@ -462,6 +469,8 @@ int launch_bulk_find_t(cc_graph* g, const int2* items, int64_t count, uint8_t* o
   int32_t* parent = g->parent;
   int32_t n = (int32_t)g->n;
   BulkFindScratch sc = g->bf;
+  // item indices of the open-item lists are 32-bit
+  if (KIND != 0 || count > (int64_t)0xffffffffLL) sc.open = nullptr;
   unsigned long long* slots = g->slots;
   int* flags = g->flags;
   unsigned spin = (unsigned)g->tune.spin_limit;
