@@ -37,7 +37,7 @@ namespace {
 // generation, bar[64] abort, bar[96 + 32 s] arrivals of sub-group s; all zero
 // at launch.
 constexpr int kBarSub = 16;
-constexpr int kBarSubMin = 128;
+constexpr int kBarSubMin = 256;
 constexpr int kBarWords = 96 + 32 * kBarSub;
 
 __device__ __forceinline__ unsigned bar_load(unsigned* p) {
