@@ -820,6 +820,8 @@ def run_serve(args):
         % (R, S, scale, tot_e, tot_q, time.perf_counter() - t))
     popts = tuning.lookup("serve", "rmat", n) or tuning.lookup("pool", "mixed", n) or {}
     popts = {k: v for k, v in popts.items() if k not in ("update_mode", "compress_every")}
+    if args.options:
+        popts.update(parse_options(args.options))
     popts["compress_linked"] = 0  # rounds overlap on two streams
 
     def with_arrivals(times):
