@@ -1016,6 +1016,70 @@ def run_components(args):
     return res
 
 
+def run_deep(args):
+    """One Bulk-Query of 2^20 uniform pairs on an uncompressed forest of long
+    paths (n = 2^24, paths of L random vertices, L = 16, 256, 4096), loaded
+    as a state image before each timed call: independent finds with and
+    without path halving against Bulk-Find (Section 5) with Phase II by
+    pointer jumping and by the response distributor.  Many endpoints share
+    each path, the case Bulk-Find's work bound is about.  Every answer is
+    checked against the paths' membership."""
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_1602_05232_amd as ccgpu
+    from paper_1602_05232_amd import roofline
+
+    n, q = 1 << 24, 1 << 20
+    pairs_h = synth.uniform_pairs(synth.key(synth.BASE_SEED + 9, 0, synth.P_QUERIES), 0, q, n)
+    pairs = torch.from_numpy(pairs_h).cuda()
+    out = torch.empty(q, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    e0, e1 = roofline.TimingEvent(), roofline.TimingEvent()
+    forms = [("independent, halving", dict(find=0, query_halving=1)),
+             ("independent, no halving", dict(find=0, query_halving=0)),
+             ("bulk-find, pointer jumping", dict(find=1)),
+             ("bulk-find, response distributor", dict(find=2))]
+    reps = max(3, args.steps)
+    table = {}
+    for L in (16, 256, 4096):
+        parent, path = synth.chain_forest(n, L)
+        want = torch.from_numpy((path[pairs_h[:, 0]] == path[pairs_h[:, 1]]).astype(np.uint8))
+        img = np.array([n, n - n // L], np.int64).tobytes() + parent.tobytes()
+        del parent, path
+        row = {}
+        for name, o in forms:
+            g = ccgpu.Graph(n, hook=0, filter=0, compress_linked=0, **o)
+            ts = []
+            for _ in range(args.warmup + reps):
+                g.load(img)
+                e0.record(stream)
+                g.bulk_query(pairs, out=out)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1))
+                if not torch.equal(out.cpu(), want):
+                    raise SystemExit("deepforest: wrong answers (L=%d, %s)" % (L, name))
+            if g.sync() != 0:
+                raise SystemExit("device reported an error (L=%d, %s)" % (L, name))
+            g.close()
+            ms = sorted(ts[args.warmup:])[reps // 2]
+            row[name] = {"ms": ms, "pairs_per_s": q / (ms * 1e-3)}
+            log("L=%d %s: %.3f ms" % (L, name, ms))
+        table["L%d" % L] = row
+    e0.close()
+    e1.close()
+    best = table["L4096"]["bulk-find, pointer jumping"]
+    res = result(best["pairs_per_s"], reps, args.warmup, 0.0, {
+        "workload": "deepforest-2^24", "n": n, "queries": q, "path_lengths": [16, 256, 4096],
+        "forest": "n / L paths of L random vertices, parent id below child id, loaded as a state image",
+        "form": "one Bulk-Query per loaded forest", "options": {"hook": 0, "filter": 0}})
+    res.update({"ms_per_step": best["ms"], "by_path_length": table,
+                "value_is": "Bulk-Find (pointer jumping) at L = 4096"})
+    return res
+
+
 def compact(r: dict, keys) -> dict:
     out = {"value": r["value"], "unit": r["unit"], "ms_per_step": r["ms_per_step"]}
     for k in keys:
@@ -1060,7 +1124,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat24",
-                    choices=["rmat24", "er16", "grid4096", "batched1024", "serve64", "bigbatch", "components"])
+                    choices=["rmat24", "er16", "grid4096", "batched1024", "serve64", "bigbatch", "components",
+                             "deepforest"])
     ap.add_argument("--requests", type=int, default=1024, help="requests of the serving trace")
     ap.add_argument("--serve-scale", type=int, default=22, help="R-MAT scale of each served graph")
     ap.add_argument("--scale", type=int, default=24, help="R-MAT scale of the rmat24 workload")
@@ -1087,7 +1152,8 @@ def main():
         import __graft_entry__
         __graft_entry__.build()
     res = {"rmat24": run_rmat, "er16": run_er, "grid4096": run_grid, "batched1024": run_batched,
-           "serve64": run_serve, "bigbatch": run_bigbatch, "components": run_components}[args.workload](args)
+           "serve64": run_serve, "bigbatch": run_bigbatch, "components": run_components,
+           "deepforest": run_deep}[args.workload](args)
     if args.workload == "rmat24" and not args.no_forms:
         res["forms"] = run_forms(args)
     print(json.dumps(res), flush=True)

@@ -372,3 +372,21 @@ def tiny_stream(n: int, edges, batches: list, queries=None) -> Stream:
     q = np.ascontiguousarray(np.asarray(queries if queries is not None else np.empty((0, 2)),
                                         np.int32).reshape(-1, 2))
     return Stream("tiny", n, e, _offsets(batches), q, _offsets([q.shape[0]] + [0] * (len(batches) - 1)))
+
+
+def chain_forest(n: int, L: int, seed=BASE_SEED + 9):
+    """A forest image of n // L paths of L vertices each (L divides n): the
+    vertices of a path are drawn at random and ordered so that every parent
+    id is below its child's, which an id-order forest may hold.  Returns
+    (parent int32[n], path int64[n]): path[v] is the index of v's path, so
+    u and v are connected iff path[u] == path[v]."""
+    if L < 1 or n % L:
+        raise ValueError("L must divide n")
+    rows = permutation(key(seed, 0, P_PERM), n).reshape(n // L, L)
+    rows.sort(axis=1)
+    parent = np.empty(n, np.int32)
+    parent[rows[:, 0]] = rows[:, 0]
+    parent[rows[:, 1:].ravel()] = rows[:, :-1].ravel()
+    path = np.empty(n, np.int64)
+    path[rows.ravel()] = np.repeat(np.arange(n // L, dtype=np.int64), L)
+    return parent, path

@@ -468,3 +468,34 @@ def test_id_order_forest_invariants(cc, opts):
         roots = int((par == np.arange(s.n)).sum())
         assert roots == g.num_components() == g.count_roots()
     g.close()
+
+
+@pytest.mark.parametrize("L", [16, 4096])
+@pytest.mark.parametrize("opts", [dict(find=0, query_halving=1), dict(find=0, query_halving=0), dict(find=1),
+                                  dict(find=2), dict(find=1, grid_cap=3)],
+                         ids=["halving", "no-halving", "find1", "find2", "find1-small-grid"])
+def test_queries_on_loaded_path_forest(cc, L, opts):
+    """Long uncompressed paths that many query ends share (the case of
+    Section 5's work bound), loaded as a state image: every answer and every
+    label against the oracle fed the same forest as edges."""
+    n = 1 << 16
+    parent, path = synth.chain_forest(n, L)
+    v = np.arange(n, dtype=np.int32)
+    kids = parent != v
+    ref = oracle.UnionFind(n)
+    ref.bulk_update(np.stack([parent[kids], v[kids]], 1))
+    k = synth.key(synth.BASE_SEED + 9, 1, synth.P_QUERIES)
+    pairs = synth.uniform_pairs(k, 0, 1 << 14, n)
+    same = np.argsort(path, kind="stable").astype(np.int32)  # path by path
+    pairs = np.concatenate([pairs, np.stack([same[:-1], same[1:]], 1)])  # mostly within one path
+    want = ref.bulk_query(pairs)
+    assert want.sum() > len(pairs) // 2  # the second half is mostly connected pairs
+    g = cc.Graph(n, hook=0, compress_linked=0, **opts)
+    img = np.array([n, n - n // L], np.int64).tobytes() + parent.tobytes()
+    g.load(img)
+    got = g.bulk_query(dev(pairs)).cpu().numpy()
+    np.testing.assert_array_equal(got, want)
+    np.testing.assert_array_equal(g.labels().cpu().numpy(), ref.labels())
+    assert g.num_components() == ref.num_components() == n // L
+    assert g.sync() == cc.cc.CC_OK
+    g.close()

@@ -79,3 +79,24 @@ def test_grid3d_and_local_recipes(built_libs):
     dd = np.abs(s.edges[:, 0].astype(np.int64) - s.edges[:, 1])
     dd = np.minimum(dd, n - dd)
     assert len(s.edges) == 5 * n and dd.max() < w and s.edges.min() >= 0 and s.edges.max() < n
+
+
+def test_chain_forest_shape(built_libs):
+    n, L = 1 << 12, 64
+    parent, path = synth.chain_forest(n, L)
+    v = np.arange(n)
+    assert parent.dtype == np.int32 and (parent <= v).all()  # an image id-order linking accepts
+    roots = parent == v
+    assert roots.sum() == n // L
+    # every vertex reaches its path's root in at most L - 1 steps, and the
+    # deepest takes exactly L - 1
+    x, depth = v.copy(), np.zeros(n, np.int64)
+    for _ in range(L):
+        nx = parent[x]
+        depth += nx != x
+        x = nx
+    assert (parent[x] == x).all() and depth.max() == L - 1
+    assert (path == path[x]).all()  # a path's vertices share its root
+    assert np.bincount(path).tolist() == [L] * (n // L)
+    p2, _ = synth.chain_forest(n, L)
+    np.testing.assert_array_equal(parent, p2)
