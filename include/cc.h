@@ -106,9 +106,11 @@ enum cc_option {
    * distributor (Section 5.1: the traversed parent pointers sorted by a hash
    * of the parent into 3x as many buckets, then handed the root level by
    * level from the roots; about 52 more bytes per traversal bound entry,
-   * 2 * (vertices + items), at most 2^31 - 1 of them).  One cooperative launch
-   * per bulk operation; scratch of about 8 bytes per vertex plus 8 bytes per
-   * item of the largest bulk operation; not available during capture. */
+   * 2 * (vertices + items), at most 2^31 - 1 of them).  Two launches per
+   * bulk operation: level 0 (every item read once) as an ordinary launch,
+   * then Phases I and II in one cooperative launch of at most 256 blocks;
+   * scratch of about 8 bytes per vertex plus 8 bytes per item of the
+   * largest bulk operation; not available during capture. */
   CC_OPT_FIND = 10,
   /* Pools only (cc_pool_run): 1 = all rounds of a run in one cooperative
    * launch, separated by device-wide barriers, instead of one launch per

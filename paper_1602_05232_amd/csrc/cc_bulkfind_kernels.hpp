@@ -44,9 +44,15 @@
 // end that never had an edge is settled as well: it answers whether its two
 // ids are equal.
 //
-// Storage: level 0 goes to one segment per block (block b takes items
-// [b * seg0_cap / 2, (b + 1) * seg0_cap / 2) and keeps the first visits of
-// their ends in [b * seg0_cap, (b + 1) * seg0_cap)).
+// Storage: level 0 runs as a kernel of its own (k_bulk_find_level0, an
+// ordinary launch as wide as the items want, with no device-wide barrier),
+// one segment per block of that launch: block b takes items
+// [b * seg0_cap / 2, (b + 1) * seg0_cap / 2), keeps the first visits of
+// their ends in [b * seg0_cap, (b + 1) * seg0_cap) and writes how many in
+// seg_n[2 b] (a Bulk-Update's open items: seg_n[2 b + 1]).  The cooperative
+// kernel that follows (k_bulk_find) reads segments b, b + G, b + 2G, ... in
+// its block b, G its own grid, which can then be narrower: every barrier
+// of Phases I and II costs more the more blocks it has.
 // Levels 1, 2, ... are appended in order to one log, so that level l + 1
 // occupies the log range reserved while level l was read.  Each level
 // reserves through a counter of its own (a ring of three, cleared two
@@ -134,8 +140,10 @@ constexpr int64_t kRdGrid = 1 << 15;
 
 struct BulkFindScratch {
   uint32_t* visited;  // n bits, all clear at rest
-  int32_t* seg0;      // level 0, seg0_cap entries per block
-  uint32_t* open;     // Bulk-Update: seg0_cap / 2 entries per block, the items level 0 left open (or null)
+  int32_t* seg0;      // level 0, seg0_cap entries per level-0 block
+  uint32_t* open;     // Bulk-Update: seg0_cap / 2 entries per level-0 block, the items left open (or null)
+  uint32_t* seg_n;    // 2 per level-0 block: entries of its segment, then its open items
+  int64_t seg_blocks; // blocks of the level-0 launch
   int32_t* log;       // levels 1, 2, ..., -1 in chunk padding
   unsigned* ctl;      // kBulkFindCtlWords, zero at launch
   int64_t seg0_cap;   // level-0 entries per block
@@ -323,34 +331,23 @@ __device__ __forceinline__ void mark_touched(uint32_t* touched, int32_t v) {
 // items: int2 array of `count` pairs (edges or query pairs); each pair's two
 // ids form S (less the items the membership bits settle).  KIND 0 =
 // Bulk-Update, 1 = Bulk-Query (answers to out).
-template <int KIND, class Ord, int PH2>
-__global__ void k_bulk_find(int32_t* __restrict__ parent, const int2* __restrict__ items, int64_t count,
-                            int32_t n, uint8_t* __restrict__ out, BulkFindScratch sc,
-                            unsigned long long* __restrict__ slots, int* __restrict__ flags, unsigned spin_limit,
-                            const uint32_t* __restrict__ member, uint32_t* __restrict__ touched_bits,
-                            const int32_t* __restrict__ member_ctl) {
-  constexpr bool R = is_ranked<Ord>::value;
-  __shared__ int wave_off[17];
-  __shared__ int red;
-  __shared__ long long chunk[3];
-  __shared__ int32_t hot_key[17];   // response distributor: per-wavefront candidates, [16] the block's hot parent
-  __shared__ int hot_votes[16];
-  __shared__ unsigned hot_ctr[3];   // hot pairs counted, placed, and the base of the block's range
-  __shared__ int pass_max[16];      // top-down phase A: longest short bucket per wavefront
-  const int B = blockDim.x, tid = threadIdx.x;
-  const int64_t gsize = (int64_t)gridDim.x * B;
-  const int64_t gtid = (int64_t)blockIdx.x * B + tid;
-  unsigned* groups = sc.ctl + kBfGroups;
-  unsigned* bar = sc.ctl + kBfBar;
-  const int slot = (int)(blockIdx.x % kCountSlots) * kCountStride;
-  unsigned gen = 0;
-  // queries: the touched bitmap, while the device says it is complete
-  const uint32_t* touched = KIND == 1 && touched_bits && touched_complete(member_ctl) ? touched_bits : nullptr;
+constexpr uint8_t kBfOpen = 2;  // a query pair left open by level 0, answered after Phase II
+constexpr int kBfLevel0MaxBlocks = 4096;  // blocks of a level-0 launch at most
+constexpr int kBfCoopBlocks = 256;        // blocks of the cooperative launch at most
 
-  // level 0: this block's share of the items (seg0_cap / 2 of them, room
-  // for both ends of each).  A query pair settled here gets its answer now,
-  // an open one the mark kOpen, answered after Phase II.
-  constexpr uint8_t kOpen = 2;
+// Level 0: every item read once, one thread per item.  An item settled here
+// (out of range, a self-loop, proved by the bitmaps) gets a query answer
+// now, an open one the mark kBfOpen, and its ends' first visits go to the
+// block's segment.  touched_bits: the touched bitmap, read by queries while
+// the device says it is complete.
+template <int KIND>
+__global__ void k_bulk_find_level0(const int2* __restrict__ items, int64_t count, int32_t n,
+                                   uint8_t* __restrict__ out, BulkFindScratch sc, int* __restrict__ flags,
+                                   const uint32_t* __restrict__ member, const uint32_t* __restrict__ touched_bits,
+                                   const int32_t* __restrict__ member_ctl) {
+  __shared__ int wave_off[17];
+  const int B = blockDim.x, tid = threadIdx.x;
+  const uint32_t* touched = KIND == 1 && touched_bits && touched_complete(member_ctl) ? touched_bits : nullptr;
   const int64_t per = sc.seg0_cap >> 1;
   const int64_t i0 = (int64_t)blockIdx.x * per;
   const int64_t i1 = i0 + per < count ? i0 + per : count;
@@ -374,7 +371,7 @@ __global__ void k_bulk_find(int32_t* __restrict__ parent, const int2* __restrict
       } else if (both_members(member, e)) {
         if (KIND == 1) out[i] = 1;
       } else {
-        if (KIND == 1) out[i] = kOpen;
+        if (KIND == 1) out[i] = kBfOpen;
         a = e.x;
         b = e.y;
       }
@@ -392,8 +389,53 @@ __global__ void k_bulk_find(int32_t* __restrict__ parent, const int2* __restrict
     cnt0 += total & 0xffff;
     nopen += total >> 16;
   }
-  if (tid == 0 && cnt0 > 0) atomicAdd(count_group(groups, 0) + slot, (unsigned)cnt0);
-  bool alive = grid_sync(bar, gen, flags, spin_limit);
+  if (tid == 0) {
+    sc.seg_n[2 * blockIdx.x] = (uint32_t)cnt0;
+    sc.seg_n[2 * blockIdx.x + 1] = (uint32_t)nopen;
+    const int slot = (int)(blockIdx.x % kCountSlots) * kCountStride;
+    if (cnt0 > 0) atomicAdd(count_group(sc.ctl + kBfGroups, 0) + slot, (unsigned)cnt0);
+  }
+}
+
+// Calls f(v) for every entry v of the level-0 segments this block reads
+// (segments blockIdx.x, + gridDim.x, ...), in block-uniform loops: every
+// thread calls f the same number of times, with v = -1 past a segment's end.
+template <class F>
+__device__ __forceinline__ void for_level0(const BulkFindScratch& sc, F&& f) {
+  const int64_t per = sc.seg0_cap >> 1;
+  for (int64_t a = blockIdx.x; a < sc.seg_blocks; a += gridDim.x) {
+    const int32_t* seg = sc.seg0 + 2 * a * per;
+    const int64_t cnt = sc.seg_n[2 * a];
+    for (int64_t base = 0; base < cnt; base += blockDim.x) {
+      const int64_t j = base + threadIdx.x;
+      f(j < cnt ? seg[j] : -1);
+    }
+  }
+}
+
+// Phases I and II and the operation itself, one cooperative launch after
+// k_bulk_find_level0 (whose writes the launch boundary publishes).
+template <int KIND, class Ord, int PH2>
+__global__ void k_bulk_find(int32_t* __restrict__ parent, const int2* __restrict__ items, int64_t count,
+                            int32_t n, uint8_t* __restrict__ out, BulkFindScratch sc,
+                            unsigned long long* __restrict__ slots, int* __restrict__ flags, unsigned spin_limit,
+                            const uint32_t* __restrict__ member, uint32_t* __restrict__ touched_bits) {
+  constexpr bool R = is_ranked<Ord>::value;
+  __shared__ int wave_off[17];
+  __shared__ int red;
+  __shared__ long long chunk[3];
+  __shared__ int32_t hot_key[17];   // response distributor: per-wavefront candidates, [16] the block's hot parent
+  __shared__ int hot_votes[16];
+  __shared__ unsigned hot_ctr[3];   // hot pairs counted, placed, and the base of the block's range
+  __shared__ int pass_max[16];      // top-down phase A: longest short bucket per wavefront
+  const int B = blockDim.x, tid = threadIdx.x;
+  const int64_t gsize = (int64_t)gridDim.x * B;
+  const int64_t gtid = (int64_t)blockIdx.x * B + tid;
+  unsigned* groups = sc.ctl + kBfGroups;
+  unsigned* bar = sc.ctl + kBfBar;
+  const int slot = (int)(blockIdx.x % kCountSlots) * kCountStride;
+  unsigned gen = 0;
+  bool alive = true;
 
   // Phase I: read level l (block-uniform loops), append level l + 1 at the
   // end of level l's log range
@@ -425,12 +467,8 @@ __global__ void k_bulk_find(int32_t* __restrict__ parent, const int2* __restrict
     }
     __syncthreads();
     int outs = 0;  // this thread's appends
-    const int64_t lo = level == 0 ? 0 : s, hi = level == 0 ? cnt0 : e;
-    const int64_t step = level == 0 ? B : gsize, first = level == 0 ? tid : gtid;
-    for (int64_t base = lo; base < hi; base += step) {
-      const int64_t j = base + first;
-      int32_t v = -1;
-      if (j < hi) v = level == 0 ? seg[j] : sc.log[j];
+    // one step up from v (-1: none), called by every thread alike
+    auto climb = [&](int32_t v) {
       if ((uint32_t)v >= (uint32_t)n) v = -1;  // chunk padding
       int32_t p = -1;
       if (v >= 0) {
@@ -439,6 +477,14 @@ __global__ void k_bulk_find(int32_t* __restrict__ parent, const int2* __restrict
       }
       outs += p >= 0;
       level_put(p >= 0, p, sc.log, next, K, chunk, wave_off, flags);
+    };
+    if (level == 0) {
+      for_level0(sc, climb);
+    } else {
+      for (int64_t base = s; base < e; base += gsize) {
+        const int64_t j = base + gtid;
+        climb(j < e ? sc.log[j] : -1);
+      }
     }
     __syncthreads();
     if (K > 0 && chunk[0] >= 0)
@@ -479,7 +525,9 @@ __global__ void k_bulk_find(int32_t* __restrict__ parent, const int2* __restrict
     //     items and the same parents, so they agree on which are hot.
     for (int64_t i = gtid; i <= (int64_t)rho; i += gsize) cnt[i] = 0u;
     {
-      const int32_t v = tid < cnt0 ? seg[tid] : -1;
+      const int64_t per0 = sc.seg0_cap >> 1;
+      const int64_t cnt_first = blockIdx.x < sc.seg_blocks ? (int64_t)sc.seg_n[2 * blockIdx.x] : 0;
+      const int32_t v = tid < cnt_first ? sc.seg0[2 * blockIdx.x * per0 + tid] : -1;
       const int32_t p = v >= 0 ? ldp<R>(parent + v) : -1;
       const bool go = v >= 0 && p != v;
       const unsigned long long m = __ballot(go);
@@ -512,14 +560,13 @@ __global__ void k_bulk_find(int32_t* __restrict__ parent, const int2* __restrict
     //     in the level's ring word)
     const LevelOut roots{ring_ctr(sc.ctl, kBfRd, 0), 0, dcap};
     int nroots = 0;
-    for (int64_t base = 0; alive && base < cnt0; base += B) {
-      const int64_t j = base + tid;
-      const int32_t v = j < cnt0 ? seg[j] : -1;
-      const int32_t p = v >= 0 ? ldp<R>(parent + v) : -1;
-      hist_add(cnt, p, rho, v >= 0 && p != v, hot, hot_ctr);
-      nroots += v >= 0 && p == v;
-      level_put(v >= 0 && p == v, make_int2(v, v), sc.rd_down, roots, kRdRootChunk, chunk, wave_off, flags);
-    }
+    if (alive)
+      for_level0(sc, [&](int32_t v) {
+        const int32_t p = v >= 0 ? ldp<R>(parent + v) : -1;
+        hist_add(cnt, p, rho, v >= 0 && p != v, hot, hot_ctr);
+        nroots += v >= 0 && p == v;
+        level_put(v >= 0 && p == v, make_int2(v, v), sc.rd_down, roots, kRdRootChunk, chunk, wave_off, flags);
+      });
     for (int64_t base = 0; alive && base < lend; base += gsize) {
       const int64_t j = base + gtid;
       int32_t v = j < lend ? sc.log[j] : -1;
@@ -577,14 +624,13 @@ __global__ void k_bulk_find(int32_t* __restrict__ parent, const int2* __restrict
     //     the block's hot pairs fill a range it reserves with one atomic
     if (tid == 0) hot_ctr[2] = (alive && hot >= 0 && hot_ctr[0] > 0u) ? atomicAdd(cnt + rd_bucket(hot, rho), hot_ctr[0]) : 0u;
     __syncthreads();
-    for (int64_t base = 0; alive && base < cnt0; base += B) {
-      const int64_t j = base + tid;
-      const int32_t v = j < cnt0 ? seg[j] : -1;
-      const int32_t p = v >= 0 ? ldp<R>(parent + v) : -1;
-      const bool go = v >= 0 && p != v;
-      const uint32_t at = scatter_slot(cnt, p, rho, go, hot, hot_ctr);
-      if (go) sc.rd_pairs[at] = make_int2(p, v);
-    }
+    if (alive)
+      for_level0(sc, [&](int32_t v) {
+        const int32_t p = v >= 0 ? ldp<R>(parent + v) : -1;
+        const bool go = v >= 0 && p != v;
+        const uint32_t at = scatter_slot(cnt, p, rho, go, hot, hot_ctr);
+        if (go) sc.rd_pairs[at] = make_int2(p, v);
+      });
     for (int64_t base = 0; alive && base < lend; base += gsize) {
       const int64_t j = base + gtid;
       int32_t v = j < lend ? sc.log[j] : -1;
@@ -718,7 +764,9 @@ __global__ void k_bulk_find(int32_t* __restrict__ parent, const int2* __restrict
   for (int round = 0; PH2 == 0 && alive; ++round) {
     if (blockIdx.x == 0 && tid == 0) st_count(ring_word(sc.ctl, kBfFlags, round + 1), 0u);
     bool moved = false;
-    for (int64_t j = tid; j < cnt0; j += B) moved |= jump<R>(parent, seg[j]);
+    for_level0(sc, [&](int32_t v) {
+      if (v >= 0) moved |= jump<R>(parent, v);
+    });
     for (int64_t j = gtid; j < lend; j += gsize) {
       const int32_t v = sc.log[j];
       if ((uint32_t)v < (uint32_t)n) moved |= jump<R>(parent, v);
@@ -731,10 +779,9 @@ __global__ void k_bulk_find(int32_t* __restrict__ parent, const int2* __restrict
       alive = false;
     }
   }
-  for (int64_t j = tid; j < cnt0; j += B) {
-    const int32_t v = seg[j];
-    atomicAnd(sc.visited + (v >> 5), ~(1u << (v & 31)));
-  }
+  for_level0(sc, [&](int32_t v) {
+    if (v >= 0) atomicAnd(sc.visited + (v >> 5), ~(1u << (v & 31)));
+  });
   for (int64_t j = gtid; j < lend; j += gsize) {
     const int32_t v = sc.log[j];
     if ((uint32_t)v < (uint32_t)n) atomicAnd(sc.visited + (v >> 5), ~(1u << (v & 31)));
@@ -744,25 +791,37 @@ __global__ void k_bulk_find(int32_t* __restrict__ parent, const int2* __restrict
   if (KIND == 1) {
     // the open pairs: both ends were climbed and point at their roots
     for (int64_t i = gtid; i < count; i += gsize) {
-      if (out[i] != kOpen) continue;
+      if (out[i] != kBfOpen) continue;
       const int2 p = items[i];
       out[i] = ldp<R>(parent + p.x) == ldp<R>(parent + p.y);
     }
   } else {
     int links = 0;
-    // every item, or only the open ones this block listed at level 0 (the
-    // others are out of range, self-loops or settled by the bits)
-    const int64_t lim = open ? nopen : count, first = open ? tid : gtid, step = open ? B : gsize;
-    for (int64_t k = first; k < lim; k += step) {
-      const int64_t i = open ? (int64_t)open[i0 + k] : k;
+    auto settle = [&](int64_t i) {
       const int2 p = items[i];
-      if (!open && (!in_range(p, n) || p.x == p.y || both_members(member, p))) continue;
       if (touched_bits) {
         mark_touched(touched_bits, p.x);
         mark_touched(touched_bits, p.y);
       }
       const int32_t ru = ldp<R>(parent + p.x), rv = ldp<R>(parent + p.y);  // roots before any link
       if (ru != rv) links += link(parent, ru, rv, n, flags, Ord{}) >= 0;
+    };
+    if (sc.open) {
+      // only the items level 0 left open, from the lists of the level-0
+      // blocks this block reads (the others are out of range, self-loops or
+      // settled by the bits)
+      const int64_t per = sc.seg0_cap >> 1;
+      for (int64_t a = blockIdx.x; a < sc.seg_blocks; a += gridDim.x) {
+        const uint32_t* list = sc.open + a * per;
+        const int64_t nopen = sc.seg_n[2 * a + 1];
+        for (int64_t k = tid; k < nopen; k += B) settle((int64_t)list[k]);
+      }
+    } else {
+      for (int64_t i = gtid; i < count; i += gsize) {
+        const int2 p = items[i];
+        if (!in_range(p, n) || p.x == p.y || both_members(member, p)) continue;
+        settle(i);
+      }
     }
     count_links(slots, links);
   }
