@@ -328,9 +328,9 @@ __device__ __forceinline__ void mark_touched(uint32_t* touched, int32_t v) {
   if (!bit_test(bit_word_l2(touched, v), v)) bit_set(touched, v);
 }
 
-// items: int2 array of `count` pairs (edges or query pairs); each pair's two
-// ids form S (less the items the membership bits settle).  KIND 0 =
-// Bulk-Update, 1 = Bulk-Query (answers to out).
+// Both kernels below take items, an int2 array of `count` pairs (edges or
+// query pairs) whose ids form S (less the items the membership bits
+// settle), and KIND 0 = Bulk-Update, 1 = Bulk-Query (answers to out).
 constexpr uint8_t kBfOpen = 2;  // a query pair left open by level 0, answered after Phase II
 constexpr int kBfLevel0MaxBlocks = 4096;  // blocks of a level-0 launch at most
 constexpr int kBfCoopBlocks = 256;        // blocks of the cooperative launch at most
