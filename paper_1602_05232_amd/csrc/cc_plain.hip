@@ -513,7 +513,15 @@ int contract_grid(cc_graph* g, int64_t m, int64_t* grid) {
   int per_cu = 0, cus = 0;
   HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_contract<Ord>, block, 0));
   HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g->device));
+  // One block per 1024 edges up to 256 blocks, then one per 16K edges, at
+  // most 1024: the rounds' device-wide barriers cost more the more blocks
+  // meet at them, and only a huge minibatch has the work to pay for width
+  // (R-MAT scale 24 in 64 / 8 / 1 minibatches, id order: 256, 512-1024 and
+  // 1024 blocks were fastest, 14.3 / 11.3 / 25.3 ms per pass, against 24.9 /
+  // 12.5 / 25.7 ms at the widest resident grid).
   int64_t b = (m + 4 * block - 1) / (4 * block);
+  b = std::min<int64_t>(b, std::max<int64_t>(256, (m + 16383) / 16384));
+  b = std::min<int64_t>(b, 1024);
   b = std::min<int64_t>(b, cc::coop_limit(per_cu, cus, block));
   b = std::min<int64_t>(b, (int64_t)g->tune.grid_cap);
   *grid = std::max<int64_t>(b, 1);
