@@ -499,3 +499,26 @@ def test_queries_on_loaded_path_forest(cc, L, opts):
     assert g.num_components() == ref.num_components() == n // L
     assert g.sync() == cc.cc.CC_OK
     g.close()
+
+
+@pytest.mark.parametrize("opts", [dict(find=1), dict(find=2, hook=2), dict(find=1, hook=2, filter=2)],
+                         ids=["find1", "find2-rank", "find1-rank-filter"])
+def test_bulk_find_wide_call(cc, opts):
+    """One Bulk-Update and one Bulk-Query of 2^20 items each, so that level 0
+    runs 2048 blocks and every block of the 256-block cooperative launch
+    reads several level-0 segments: every answer and label is the oracle's."""
+    n = 1 << 20
+    k = synth.key(synth.BASE_SEED + 11, 0, synth.P_EDGES)
+    first = synth.rmat_edges(k, 0, 1 << 18, 20, n)
+    edges = synth.rmat_edges(k, 1 << 18, 1 << 20, 20, n)
+    pairs = synth.uniform_pairs(synth.key(synth.BASE_SEED + 11, 0, synth.P_QUERIES), 0, 1 << 20, n)
+    ref = oracle.UnionFind(n)
+    g = cc.Graph(n, **opts)
+    for e in (first, edges):  # a first call, so that the filter has an anchor for the wide one
+        ref.bulk_update(e)
+        g.bulk_update(dev(e))
+    np.testing.assert_array_equal(g.bulk_query(dev(pairs)).cpu().numpy(), ref.bulk_query(pairs))
+    np.testing.assert_array_equal(g.labels().cpu().numpy(), ref.labels())
+    assert g.num_components() == ref.num_components()
+    assert g.sync() == cc.cc.CC_OK
+    g.close()
